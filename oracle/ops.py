@@ -1,0 +1,306 @@
+"""Oracle operators: Liouville operator, collision term, inflow mask, right-hand side,
+spectral filter, and the exact transposes used by the discrete adjoint.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Array layout: F[eps][r][theta][phi][Theta][Phi] (axes 0..5), FP64.
+
+Readings of the paper used here (each is listed in the design notes):
+
+* Eq. (sing) in Sect. 4.1 prints cos(Phi) in front of the singular phi and Phi
+  derivatives; Eq. (Liouvsph) and the conservative form of App. A
+  (Eq. Cohercons) have sin(Phi), and only sin(Phi) gives L omega_i = 0
+  (Eq. prop2).  The operator below follows Eq. (Liouvsph).
+* theta and Theta derivatives use double-Fourier-sphere lines: the point
+  (-theta, phi, Theta, Phi) is the point (theta, phi + pi, Theta, Phi + pi), and
+  the direction (-Theta, Phi) is the direction (Theta, Phi + pi) (both follow
+  from Eqs. omegax-omegaz).  Nodes are half-shifted, so no node sits on a pole
+  or on Theta = pi/2.
+* The collision term is Eq. (Transp) with coherent scattering
+  (Eq. sigmadif), the isotropic kernel (Eq. sigman with B = 0), the density
+  absorbed into kappa = n sigma_a, sigma = n A, eta = n S, and without the
+  induced-process factors (they make the equation nonlinear):
+      C(F) = eta - (kappa + sigma) F + sigma <F>,
+      <F>  = (1/4pi) sum_i sum_m w_i (2pi/n_Phi) F_im   (Fejer in cos Theta).
+* Inflow (Sect. 4.2, Eq. Sphedif): F is imposed at r = r_in where
+  cos(Theta) > 0 and at r = r_out where cos(Theta) < 0; the right-hand side is
+  set to zero there (a collocation analogue of the paper's Tau imposition).
+"""
+
+import numpy as np
+
+AX_EPS, AX_R, AX_TH, AX_PH, AX_TTH, AX_TPH = range(6)
+
+
+def apply_along(D, F, axis):
+    """(D F) along one axis: out[..., i, ...] = sum_k D[i, k] F[..., k, ...]."""
+    out = np.tensordot(D, F, axes=([1], [axis]))
+    return np.moveaxis(out, 0, axis)
+
+
+# ---------------------------------------------------------------------------
+# the five 1D derivatives
+
+
+def d_r(F, g):
+    """Chebyshev collocation derivative along r."""
+    return apply_along(g.D_r, F, AX_R)
+
+
+def d_phi(F, g):
+    """Fourier derivative along phi (periodic, n_phi points)."""
+    return apply_along(g.D_phi, F, AX_PH)
+
+
+def d_Phi(F, g):
+    """Fourier derivative along Phi (periodic, n_Phi points)."""
+    return apply_along(g.D_Phi, F, AX_TPH)
+
+
+def dfs_extend_theta(F, g):
+    """Build the 2 n_theta periodic DFS line in theta for every (phi_k, Phi_m).
+
+    Entry i < n_theta is F(theta_i, phi_k, Phi_m); entry 2 n_theta - 1 - i is the
+    value at colatitude -theta_i, i.e. F(theta_i, phi_k + pi, Phi_m + pi).
+    """
+    partner = np.roll(np.roll(F, -(g.n_phi // 2), axis=AX_PH), -(g.n_Phi // 2), axis=AX_TPH)
+    return np.concatenate([F, np.flip(partner, axis=AX_TH)], axis=AX_TH)
+
+
+def dfs_extend_theta_T(G, g):
+    """Transpose of dfs_extend_theta: fold the 2 n_theta line back onto F's shape."""
+    n = g.n_theta
+    head = np.take(G, np.arange(n), axis=AX_TH)
+    tail = np.flip(np.take(G, np.arange(n, 2 * n), axis=AX_TH), axis=AX_TH)
+    back = np.roll(np.roll(tail, g.n_phi // 2, axis=AX_PH), g.n_Phi // 2, axis=AX_TPH)
+    return head + back
+
+
+def dfs_extend_Theta(F, g):
+    """Build the 2 n_Theta periodic DFS line in Theta for every Phi_m.
+
+    Entry i < n_Theta is F(Theta_i, Phi_m); entry 2 n_Theta - 1 - i is the value
+    at -Theta_i, i.e. F(Theta_i, Phi_m + pi).
+    """
+    partner = np.roll(F, -(g.n_Phi // 2), axis=AX_TPH)
+    return np.concatenate([F, np.flip(partner, axis=AX_TTH)], axis=AX_TTH)
+
+
+def dfs_extend_Theta_T(G, g):
+    n = g.n_Theta
+    head = np.take(G, np.arange(n), axis=AX_TTH)
+    tail = np.flip(np.take(G, np.arange(n, 2 * n), axis=AX_TTH), axis=AX_TTH)
+    return head + np.roll(tail, g.n_Phi // 2, axis=AX_TPH)
+
+
+def d_theta(F, g):
+    """DFS Fourier derivative along theta: differentiate the 2 n_theta line, keep
+    the first n_theta entries (the derivative at theta_i for this (phi_k, Phi_m))."""
+    G = apply_along(g.D_theta, dfs_extend_theta(F, g), AX_TH)
+    return np.take(G, np.arange(g.n_theta), axis=AX_TH)
+
+
+def d_Theta(F, g):
+    """DFS Fourier derivative along Theta (within each (Theta, Phi) plane)."""
+    G = apply_along(g.D_Theta, dfs_extend_Theta(F, g), AX_TTH)
+    return np.take(G, np.arange(g.n_Theta), axis=AX_TTH)
+
+
+def _pad_half(X, axis, n):
+    """Transpose of 'keep the first n of 2n entries': zero-pad to length 2n."""
+    shape = list(X.shape)
+    shape[axis] = n
+    return np.concatenate([X, np.zeros(shape)], axis=axis)
+
+
+def d_theta_T(X, g):
+    """Exact transpose of d_theta."""
+    G = _pad_half(X, AX_TH, g.n_theta)
+    return dfs_extend_theta_T(apply_along(g.D_theta.T, G, AX_TH), g)
+
+
+def d_Theta_T(X, g):
+    """Exact transpose of d_Theta."""
+    G = _pad_half(X, AX_TTH, g.n_Theta)
+    return dfs_extend_Theta_T(apply_along(g.D_Theta.T, G, AX_TTH), g)
+
+
+# ---------------------------------------------------------------------------
+# the Liouville operator, Eq. (Liouvsph)
+
+
+def liouville_coefficients(g):
+    """Pointwise coefficients of the five terms of Eq. (Liouvsph), rank-6 broadcastable:
+        c_r   = cos Theta
+        c_th  = sin Theta cos Phi / r
+        c_ph  = sin Theta sin Phi / (r sin theta)
+        c_Th  = -sin Theta / r
+        c_Ph  = -sin Theta sin Phi cos theta / (r sin theta)
+    """
+    r, th, ph, Th, Ph = g.mesh()
+    c_r = np.cos(Th) + 0.0 * r
+    c_th = np.sin(Th) * np.cos(Ph) / r
+    c_ph = np.sin(Th) * np.sin(Ph) / (r * np.sin(th))
+    c_Th = -np.sin(Th) / r + 0.0 * Ph
+    c_Ph = -np.sin(Th) * np.sin(Ph) * np.cos(th) / (r * np.sin(th))
+    return c_r, c_th, c_ph, c_Th, c_Ph
+
+
+def apply_L(F, g):
+    """L_sph F, Eq. (Liouvsph): the sum of the r, theta, phi, Theta, Phi terms."""
+    c_r, c_th, c_ph, c_Th, c_Ph = liouville_coefficients(g)
+    return (c_r * d_r(F, g) + c_th * d_theta(F, g) + c_ph * d_phi(F, g)
+            + c_Th * d_Theta(F, g) + c_Ph * d_Phi(F, g))
+
+
+def apply_LT(G, g):
+    """Exact transpose of apply_L (as a matrix on the nodal values):
+    sum over directions of D_dir^T (c_dir * G)."""
+    c_r, c_th, c_ph, c_Th, c_Ph = liouville_coefficients(g)
+    return (apply_along(g.D_r.T, c_r * G, AX_R)
+            + d_theta_T(c_th * G, g)
+            + apply_along(g.D_phi.T, c_ph * G, AX_PH)
+            + d_Theta_T(c_Th * G, g)
+            + apply_along(g.D_Phi.T, c_Ph * G, AX_TPH))
+
+
+# ---------------------------------------------------------------------------
+# collision term and boundary mask
+
+
+def angular_mean(F, g):
+    """<F> = (1/4pi) sum_i sum_m w_i (2pi/n_Phi) F[..., i, m], kept as a rank-6
+    array of shape (..., 1, 1)."""
+    w = g.w_Theta[:, None] * (2.0 * np.pi / g.n_Phi) / (4.0 * np.pi)
+    return np.sum(F * w, axis=(AX_TTH, AX_TPH), keepdims=True)
+
+
+def angular_mean_T(X, g):
+    """Transpose of F -> broadcast(<F>): sum X over the plane, times the weights."""
+    w = g.w_Theta[:, None] * (2.0 * np.pi / g.n_Phi) / (4.0 * np.pi)
+    return np.sum(X, axis=(AX_TTH, AX_TPH), keepdims=True) * w
+
+
+def expand_coeff(c, g):
+    """Isotropic coefficient field [eps][r][theta][phi] -> rank-6 broadcastable."""
+    c = np.asarray(c, dtype=np.float64)
+    return c.reshape(g.n_eps, g.n_r, g.n_theta, g.n_phi, 1, 1)
+
+
+def collision(F, g, kappa, sigma, eta):
+    """C(F) = eta - (kappa + sigma) F + sigma <F>  (see the module docstring)."""
+    k = expand_coeff(kappa, g)
+    s = expand_coeff(sigma, g)
+    e = expand_coeff(eta, g)
+    return e - (k + s) * F + s * angular_mean(F, g)
+
+
+def inflow_mask(g):
+    """1 where F evolves, 0 at the inflow nodes (r_in, cos Theta > 0) and
+    (r_out, cos Theta < 0); shape (1, n_r, 1, 1, n_Theta, 1)."""
+    m = np.ones((1, g.n_r, 1, 1, g.n_Theta, 1))
+    cT = np.cos(g.Theta)
+    m[0, 0, 0, 0, cT > 0, 0] = 0.0
+    m[0, g.n_r - 1, 0, 0, cT < 0, 0] = 0.0
+    return m
+
+
+def project_inflow(F, g, g_in=None, g_out=None):
+    """Set F to the inflow values at the inflow nodes (zero where g_* is None).
+    g_in, g_out: [eps][theta][phi][Theta][Phi]."""
+    F = F.copy()
+    cT = np.cos(g.Theta)
+    pin = np.zeros(F[:, 0].shape) if g_in is None else np.asarray(g_in, np.float64)
+    pout = np.zeros(F[:, -1].shape) if g_out is None else np.asarray(g_out, np.float64)
+    F[:, 0, :, :, cT > 0, :] = pin[:, :, :, cT > 0, :]
+    F[:, -1, :, :, cT < 0, :] = pout[:, :, :, cT < 0, :]
+    return F
+
+
+def rhs(F, g, kappa, sigma, eta, bc=True, scattering=True):
+    """Right-hand side dF/dt = -L_sph F + C(F) (Eqs. Transpfpsph, Transp), set to
+    zero at the inflow nodes when bc is True."""
+    s = sigma if scattering else np.zeros_like(np.asarray(sigma, np.float64))
+    out = -apply_L(F, g) + collision(F, g, kappa, s, eta)
+    if bc:
+        out = out * inflow_mask(g)
+    return out
+
+
+def rhs_linear_T(X, g, kappa, sigma, bc=True, scattering=True):
+    """Transpose of the linear part of rhs (A^T X, with A = M(-L - (k+s) + s avg))."""
+    if bc:
+        X = X * inflow_mask(g)
+    k = expand_coeff(kappa, g)
+    s = expand_coeff(sigma, g) if scattering else 0.0 * k
+    return -apply_LT(X, g) - (k + s) * X + angular_mean_T(s * X, g)
+
+
+# ---------------------------------------------------------------------------
+# spectral filter
+
+
+def filter_matrix(n):
+    """Grid-space form of the exponential filter exp(-36 (|k|/(n/2))^36) on a
+    periodic line of n points (the paper only mentions adding viscosity in
+    coefficient space, App. B; the filter shape is this build's reading).
+    Returns the symmetric n x n matrix F_jl = (1/n) sum_k s(k) cos(k (x_j - x_l))
+    over k = -n/2 .. n/2 - 1, with the Nyquist term taken as a cosine."""
+    j = np.arange(n)
+    M = np.zeros((n, n))
+    for k in range(-(n // 2), n // 2):
+        s = np.exp(-36.0 * (abs(k) / (n / 2.0)) ** 36)
+        M += s * np.cos(2.0 * np.pi * k * (j[:, None] - j[None, :]) / n)
+    return M / n
+
+
+def apply_filter(F, g):
+    """Filter every theta (DFS), phi, Theta (DFS) and Phi line, in that order.
+    The radial direction is not filtered."""
+    Ft = filter_matrix(2 * g.n_theta)
+    G = apply_along(Ft, dfs_extend_theta(F, g), AX_TH)
+    F = np.take(G, np.arange(g.n_theta), axis=AX_TH)
+    F = apply_along(filter_matrix(g.n_phi), F, AX_PH)
+    FT = filter_matrix(2 * g.n_Theta)
+    G = apply_along(FT, dfs_extend_Theta(F, g), AX_TTH)
+    F = np.take(G, np.arange(g.n_Theta), axis=AX_TTH)
+    F = apply_along(filter_matrix(g.n_Phi), F, AX_TPH)
+    return F
+
+
+# ---------------------------------------------------------------------------
+# single-point evaluation (for sampled checks of large grids)
+
+
+def rhs_at(F, g, kappa, sigma, eta, idx, bc=True, scattering=True):
+    """The right-hand side at a single node idx = (e, j, l, k, i, m), computed
+    from the five lines through that node and its (Theta, Phi) plane only.
+    F may be any array-like indexable by numpy (e.g. a memory map)."""
+    e, j, l, k, i, m = idx
+    nth, nph, nTh, nPh = g.n_theta, g.n_phi, g.n_Theta, g.n_Phi
+    kp, mp = (k + nph // 2) % nph, (m + nPh // 2) % nPh
+    r, th, Th, Ph = g.r[j], g.theta[l], g.Theta[i], g.Phi[m]
+    line_r = np.asarray(F[e, :, l, k, i, m], np.float64)
+    dr = g.D_r[j] @ line_r
+    th_line = np.concatenate([np.asarray(F[e, j, :, k, i, m], np.float64),
+                              np.asarray(F[e, j, :, kp, i, mp], np.float64)[::-1]])
+    dth = g.D_theta[l] @ th_line
+    dph = g.D_phi[k] @ np.asarray(F[e, j, l, :, i, m], np.float64)
+    plane = np.asarray(F[e, j, l, k], np.float64)
+    Th_line = np.concatenate([plane[:, m], plane[:, mp][::-1]])
+    dTh = g.D_Theta[i] @ Th_line
+    dPh = g.D_Phi[m] @ plane[i, :]
+    LF = (np.cos(Th) * dr + np.sin(Th) * np.cos(Ph) / r * dth
+          + np.sin(Th) * np.sin(Ph) / (r * np.sin(th)) * dph
+          - np.sin(Th) / r * dTh
+          - np.sin(Th) * np.sin(Ph) * np.cos(th) / (r * np.sin(th)) * dPh)
+    ka, si, et = (float(np.asarray(c)[e, j, l, k]) for c in (kappa, sigma, eta))
+    if not scattering:
+        si = 0.0
+    mean = np.sum(plane * g.w_Theta[:, None]) * (2.0 * np.pi / nPh) / (4.0 * np.pi)
+    out = -LF + et - (ka + si) * plane[i, m] + si * mean
+    if bc:
+        cT = np.cos(Th)
+        if (j == 0 and cT > 0) or (j == g.n_r - 1 and cT < 0):
+            out = 0.0
+    return out

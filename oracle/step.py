@@ -1,0 +1,67 @@
+"""Oracle time stepping: classical RK4 on dF/dt = -L_sph F + C(F).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The paper advances its spectral coefficients with second-order Adams-Bashforth
+(Sect. 5.1); this hot path uses classical fourth-order Runge-Kutta instead.
+Inflow data are constant in time, so the stages carry no explicit time.
+The optional filter (ops.apply_filter) is applied after each full step.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import ops
+
+
+@dataclass
+class Physics:
+    """Coefficient fields [eps][r][theta][phi] and switches."""
+
+    kappa: np.ndarray
+    sigma: np.ndarray
+    eta: np.ndarray
+    bc: bool = True
+    scattering: bool = True
+    filt: bool = False
+
+    @staticmethod
+    def vacuum(g, bc=True):
+        z = np.zeros((g.n_eps, g.n_r, g.n_theta, g.n_phi))
+        return Physics(z, z.copy(), z.copy(), bc=bc, scattering=False)
+
+
+def rhs(F, g, p):
+    return ops.rhs(F, g, p.kappa, p.sigma, p.eta, bc=p.bc, scattering=p.scattering)
+
+
+def rk4_stages(y, g, p, dt):
+    """The four stage inputs Y_s and slopes k_s of one classical RK4 step."""
+    Y1 = y
+    k1 = rhs(Y1, g, p)
+    Y2 = y + 0.5 * dt * k1
+    k2 = rhs(Y2, g, p)
+    Y3 = y + 0.5 * dt * k2
+    k3 = rhs(Y3, g, p)
+    Y4 = y + dt * k3
+    k4 = rhs(Y4, g, p)
+    return (Y1, Y2, Y3, Y4), (k1, k2, k3, k4)
+
+
+def rk4_step(y, g, p, dt):
+    """y_{n+1} = y + dt/6 (k1 + 2 k2 + 2 k3 + k4), then the filter if enabled."""
+    _, (k1, k2, k3, k4) = rk4_stages(y, g, p, dt)
+    y1 = y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    if p.filt:
+        y1 = ops.apply_filter(y1, g)
+    return y1
+
+
+def run(y, g, p, dt, n_steps, callback=None):
+    """n_steps RK4 steps from y; callback(n, y) after each step if given."""
+    for n in range(n_steps):
+        y = rk4_step(y, g, p, dt)
+        if callback is not None:
+            callback(n + 1, y)
+    return y

@@ -1,0 +1,267 @@
+"""Seeded fields sampled at the grid nodes.
+
+Node positions: r_j = (r_in + r_out)/2 - (r_out - r_in)/2 cos(pi j/(n_r - 1)),
+theta_l = (l + 1/2) pi / n_theta, phi_k = 2 pi k / n_phi,
+Theta_i = (i + 1/2) pi / n_Theta, Phi_m = 2 pi m / n_Phi.
+
+Every random field is a Cartesian function of (x, omega) or is symmetrised
+under the two double-Fourier-sphere identities, so it is a consistent function
+on the sphere of positions and the sphere of directions.
+
+All generators return float64 numpy arrays in the layout
+[eps][r][theta][phi][Theta][Phi] (states) or [eps][r][theta][phi] (coefficients).
+"""
+
+import itertools
+import math
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# sampling points
+
+
+def nodes(cfg):
+    j = np.arange(cfg.n_r)
+    r = 0.5 * (cfg.r_in + cfg.r_out) - 0.5 * (cfg.r_out - cfg.r_in) * np.cos(np.pi * j / (cfg.n_r - 1))
+    th = (np.arange(cfg.n_theta) + 0.5) * np.pi / cfg.n_theta
+    ph = 2.0 * np.pi * np.arange(cfg.n_phi) / cfg.n_phi
+    Th = (np.arange(cfg.n_Theta) + 0.5) * np.pi / cfg.n_Theta
+    Ph = 2.0 * np.pi * np.arange(cfg.n_Phi) / cfg.n_Phi
+    return r, th, ph, Th, Ph
+
+
+def _mesh5(cfg, r_sel=slice(None)):
+    r, th, ph, Th, Ph = nodes(cfg)
+    return (r[r_sel][:, None, None, None, None], th[None, :, None, None, None],
+            ph[None, None, :, None, None], Th[None, None, None, :, None],
+            Ph[None, None, None, None, :])
+
+
+def _cart(r, th, ph, Th, Ph):
+    """Unit position vector and direction vector (local-frame construction of the
+    direction: cos Theta e_r + sin Theta (cos Phi e_theta + sin Phi e_phi))."""
+    er = (np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th) + 0.0 * ph)
+    et = (np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), -np.sin(th) + 0.0 * ph)
+    ep = (-np.sin(ph) + 0.0 * th, np.cos(ph) + 0.0 * th, 0.0 * (th + ph))
+    om = tuple(np.cos(Th) * er[a] + np.sin(Th) * (np.cos(Ph) * et[a] + np.sin(Ph) * ep[a])
+               for a in range(3))
+    return er, om
+
+
+def _cheb_T(a, xi):
+    return np.cos(a * np.arccos(np.clip(xi, -1.0, 1.0)))
+
+
+def _monomials(deg):
+    """Exponent triples of total degree <= deg in graded-lex order."""
+    out = []
+    for d in range(deg + 1):
+        for e in itertools.product(range(d + 1), repeat=3):
+            if sum(e) == d:
+                out.append(e)
+    out.sort(key=lambda e: (sum(e), tuple(-x for x in e)))
+    return out
+
+
+def _xi(cfg, r):
+    return (2.0 * r - cfg.r_in - cfg.r_out) / (cfg.r_out - cfg.r_in)
+
+
+def _broadcast_eps(cfg, f5):
+    return np.ascontiguousarray(np.broadcast_to(f5[None], cfg.shape)).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# initial states
+
+
+def beam(cfg, seed=0, width=0.5, noise=1e-3):
+    """Gaussian beam exp(-|x - x_c|^2 / (2 w^2)) times the clipped lobe
+    max(0, omega . d)^4, plus `noise` times a random polynomial field normalised
+    to max |N| = 1.  x_c = 2 u with u uniform on the unit sphere (first draw of
+    default_rng(seed)); d = u (radially outward beam).  The noise field is
+    sum c T_a(xi(r)) xhat^alpha omega^beta over a <= 3, |alpha| <= 3,
+    |beta| <= 3 with c ~ N(0, 1) drawn in C order over [a][alpha][beta]."""
+    rng = np.random.default_rng(seed)
+    u = rng.normal(size=3)
+    u /= np.linalg.norm(u)
+    xc = 2.0 * u
+    r, th, ph, Th, Ph = _mesh5(cfg)
+    er, om = _cart(r, th, ph, Th, Ph)
+    x = [r * er[a] for a in range(3)]
+    d2 = sum((x[a] - xc[a]) ** 2 for a in range(3))
+    odot = sum(om[a] * u[a] for a in range(3))
+    F = np.exp(-d2 / (2.0 * width ** 2)) * np.maximum(0.0, odot) ** 4
+    mons = _monomials(3)
+    c = rng.normal(size=(4, len(mons), len(mons)))
+    xi = _xi(cfg, r)
+    xm = [er[0] ** e[0] * er[1] ** e[1] * er[2] ** e[2] for e in mons]
+    om_m = [om[0] ** e[0] * om[1] ** e[1] * om[2] ** e[2] for e in mons]
+    N = 0.0
+    for a in range(4):
+        Ta = _cheb_T(a, xi)
+        inner = 0.0
+        for ia, xa in enumerate(xm):
+            s = 0.0
+            for ib, ob in enumerate(om_m):
+                s = s + c[a, ia, ib] * ob
+            inner = inner + xa * s
+        N = N + Ta * inner
+    N = np.broadcast_to(N, F.shape)
+    F = F + noise * N / np.max(np.abs(N))
+    return _broadcast_eps(cfg, F)
+
+
+def polynomial_state(cfg, seed=0, deg_x=2, deg_om=2, scale=1.0):
+    """A random Cartesian polynomial P(x) Q(omega) with total degree deg_x in x
+    and deg_om in omega (exactly representable on the grid when the angular
+    degree is below half the smallest Fourier line)."""
+    rng = np.random.default_rng(seed)
+    r, th, ph, Th, Ph = _mesh5(cfg)
+    er, om = _cart(r, th, ph, Th, Ph)
+    x = [r * er[a] for a in range(3)]
+    mx, mo = _monomials(deg_x), _monomials(deg_om)
+    cx, co = rng.normal(size=len(mx)), rng.normal(size=len(mo))
+    P = sum(cx[i] * x[0] ** e[0] * x[1] ** e[1] * x[2] ** e[2] for i, e in enumerate(mx))
+    Q = sum(co[i] * om[0] ** e[0] * om[1] ** e[1] * om[2] ** e[2] for i, e in enumerate(mo))
+    return _broadcast_eps(cfg, scale * np.broadcast_to(P * Q, np.broadcast_shapes(np.shape(P), np.shape(Q))))
+
+
+def smooth_random_G(cfg, seed=0, kmax=10, device=None):
+    """Smooth anisotropic random field G, normalised to max |G| = 1:
+    the real part of sum c T_a(xi(r)) exp(i (k1 theta + k2 phi + k3 Theta + k4 Phi))
+    over a + |k1| + |k2| + |k3| + |k4| <= kmax, with c ~ N(0, 1) 2^-(a + |k|)
+    (drawn in C order over [a][k1][k2][k3][k4], k from -kmax to kmax), averaged
+    over the group generated by (theta, phi, Phi) -> (-theta, phi + pi, Phi + pi)
+    and (Theta, Phi) -> (-Theta, Phi + pi).  Evaluated as a separable
+    contraction with torch (on `device` if given).  Returns shape
+    [r][theta][phi][Theta][Phi]."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    n = 2 * kmax + 1
+    k = np.arange(-kmax, kmax + 1)
+    a = np.arange(kmax + 1)
+    C = rng.normal(size=(kmax + 1, n, n, n, n))
+    deg = (a[:, None, None, None, None] + np.abs(k)[None, :, None, None, None]
+           + np.abs(k)[None, None, :, None, None] + np.abs(k)[None, None, None, :, None]
+           + np.abs(k)[None, None, None, None, :])
+    C = np.where(deg <= kmax, C * 2.0 ** (-deg.astype(np.float64)), 0.0)
+    sphi = ((-1.0) ** np.abs(k))[None, None, :, None, None]
+    sPhi = ((-1.0) ** np.abs(k))[None, None, None, None, :]
+    Cs = 0.25 * (C + sphi * sPhi * C[:, ::-1] + sPhi * C[:, :, :, ::-1]
+                 + sphi * C[:, ::-1, :, ::-1])
+    r, th, ph, Th, Ph = nodes(cfg)
+    dev = torch.device(device) if device is not None else torch.device("cpu")
+    T = torch.tensor(np.stack([_cheb_T(ai, _xi(cfg, r)) for ai in a], axis=1), dtype=torch.complex128, device=dev)
+    kk = torch.tensor(k, dtype=torch.float64, device=dev)
+
+    def E(x):
+        xx = torch.tensor(x, dtype=torch.float64, device=dev)
+        return torch.exp(1j * kk[:, None] * xx[None, :])  # [k][node]
+
+    X = torch.tensor(Cs, dtype=torch.complex128, device=dev)
+    X = torch.tensordot(X, E(Ph), dims=([4], [0]))  # a k1 k2 k3 Ph
+    X = torch.tensordot(X, E(Th), dims=([3], [0]))  # a k1 k2 Ph Th
+    X = torch.tensordot(X, E(ph), dims=([2], [0]))  # a k1 Ph Th ph
+    X = torch.tensordot(X, E(th), dims=([1], [0]))  # a Ph Th ph th
+    out = torch.empty((cfg.n_r, cfg.n_theta, cfg.n_phi, cfg.n_Theta, cfg.n_Phi), dtype=torch.float64, device=dev)
+    Xp = X.permute(0, 4, 3, 2, 1).contiguous()  # a th ph Th Ph
+    for j in range(cfg.n_r):
+        out[j] = torch.tensordot(T[j], Xp, dims=([0], [0])).real
+    out /= out.abs().max()
+    return out if device is not None else out.numpy()
+
+
+def shell_state(cfg, seed=0, device=None):
+    """(r - r_in)(r_out - r) [1 + 0.5 G] for every energy group; zero on both
+    radial boundaries, so it satisfies zero inflow."""
+    G = smooth_random_G(cfg, seed=seed, device=device)
+    r = nodes(cfg)[0]
+    if device is not None:
+        import torch
+        rr = torch.tensor((r - cfg.r_in) * (cfg.r_out - r), dtype=torch.float64, device=G.device)
+        f = rr[:, None, None, None, None] * (1.0 + 0.5 * G)
+        return f.unsqueeze(0).expand(cfg.n_eps, *f.shape).contiguous()
+    f = ((r - cfg.r_in) * (cfg.r_out - r))[:, None, None, None, None] * (1.0 + 0.5 * G)
+    return _broadcast_eps(cfg, f)
+
+
+def low_mode_position_field(cfg, seed=0, deg=4):
+    """rho(r, theta, phi) = sum c T_a(xi) xhat^alpha over a, |alpha| <= deg,
+    c ~ N(0, 1) from default_rng(seed), normalised to max |rho| = 1.
+    Shape [r][theta][phi]."""
+    rng = np.random.default_rng(seed)
+    r, th, ph, _, _ = nodes(cfg)
+    R, TH, PH = np.meshgrid(r, th, ph, indexing="ij")
+    xh = (np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH))
+    mons = _monomials(deg)
+    c = rng.normal(size=(deg + 1, len(mons)))
+    rho = 0.0
+    for a in range(deg + 1):
+        Ta = _cheb_T(a, _xi(cfg, R))
+        for i, e in enumerate(mons):
+            rho = rho + c[a, i] * Ta * xh[0] ** e[0] * xh[1] ** e[1] * xh[2] ** e[2]
+    return rho / np.max(np.abs(rho))
+
+
+# ---------------------------------------------------------------------------
+# coefficient fields
+
+
+def planck_like(eps, T):
+    """2 eps^2 / (exp(eps / T) - 1)."""
+    return 2.0 * eps ** 2 / np.expm1(eps / T)
+
+
+def coefficients(cfg, kappa_s=None):
+    """(kappa, sigma, eta), each [eps][r][theta][phi]:
+    kappa = kappa0 (eps/10)^2 kappa_s with kappa_s = r^-2 unless given,
+    eta = kappa B(eps, T0 / r), sigma = kappa / 2 for the "scatter" physics and
+    0 otherwise; all zero for "vacuum"."""
+    shp = (cfg.n_eps, cfg.n_r, cfg.n_theta, cfg.n_phi)
+    if cfg.physics == "vacuum":
+        z = np.zeros(shp)
+        return z, z.copy(), z.copy()
+    r = nodes(cfg)[0]
+    eps = np.asarray(cfg.eps)[:, None, None, None]
+    if kappa_s is None:
+        kappa_s = np.broadcast_to((r ** -2.0)[:, None, None], shp[1:])
+    kappa = cfg.kappa0 * (eps / 10.0) ** 2 * np.asarray(kappa_s)[None]
+    T = cfg.T0 / r[None, :, None, None]
+    eta = kappa * planck_like(eps, T)
+    sigma = 0.5 * kappa if cfg.physics == "scatter" else np.zeros(shp)
+    return (np.ascontiguousarray(kappa, dtype=np.float64), np.ascontiguousarray(sigma, dtype=np.float64),
+            np.ascontiguousarray(eta, dtype=np.float64))
+
+
+def uniform_coefficients(cfg, kappa_val, eta_val, sigma_val=0.0):
+    """Spatially uniform (kappa, sigma, eta) per energy group (arrays over eps)."""
+    shp = (cfg.n_eps, cfg.n_r, cfg.n_theta, cfg.n_phi)
+    f = lambda v: np.ascontiguousarray(np.broadcast_to(np.asarray(v, np.float64).reshape(-1, 1, 1, 1), shp))  # noqa: E731
+    return f(kappa_val), f(sigma_val), f(eta_val)
+
+
+def random_state(cfg, seed=0):
+    """Unstructured N(0,1) nodal values (for operator-level parity only; not a
+    consistent function on the spheres)."""
+    return np.random.default_rng(seed).normal(size=cfg.shape)
+
+
+def random_coeffs(cfg, seed=0):
+    rng = np.random.default_rng(seed)
+    shp = (cfg.n_eps, cfg.n_r, cfg.n_theta, cfg.n_phi)
+    return (rng.uniform(0.1, 2.0, size=shp), rng.uniform(0.0, 1.0, size=shp), rng.uniform(0.0, 3.0, size=shp))
+
+
+def inflow_planes(cfg, seed=0):
+    """Random inflow planes [eps][theta][phi][Theta][Phi] at r_in and r_out."""
+    rng = np.random.default_rng(seed)
+    shp = (cfg.n_eps, cfg.n_theta, cfg.n_phi, cfg.n_Theta, cfg.n_Phi)
+    return rng.normal(size=shp), rng.normal(size=shp)
+
+
+def math_prod(xs):
+    return math.prod(xs)
