@@ -212,8 +212,11 @@ def project_inflow(F, g, g_in=None, g_out=None):
     cT = np.cos(g.Theta)
     pin = np.zeros(F[:, 0].shape) if g_in is None else np.asarray(g_in, np.float64)
     pout = np.zeros(F[:, -1].shape) if g_out is None else np.asarray(g_out, np.float64)
-    F[:, 0, :, :, cT > 0, :] = pin[:, :, :, cT > 0, :]
-    F[:, -1, :, :, cT < 0, :] = pout[:, :, :, cT < 0, :]
+    for i in range(g.n_Theta):
+        if cT[i] > 0:
+            F[:, 0, :, :, i, :] = pin[:, :, :, i, :]
+        elif cT[i] < 0:
+            F[:, -1, :, :, i, :] = pout[:, :, :, i, :]
     return F
 
 

@@ -1,0 +1,617 @@
+// C ABI of the 6D spectral transport hot path: handle management, host-side
+// argument validation and the kernel sequences of apply_L, rhs, step and
+// adjoint_step.  No exception crosses the interface.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sp6_internal.h"
+
+hipError_t launch_filter_columns(const KDims& d, const KTab& t, double* F, hipStream_t s);
+
+namespace {
+
+thread_local std::string g_err;
+
+sp6_status fail(sp6_status code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+sp6_status hip_fail(hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  (void)hipGetLastError();
+  return fail(SP6_ERR_HIP, m);
+}
+
+#define HIP_TRY(expr, where)                   \
+  do {                                         \
+    hipError_t _e = (expr);                    \
+    if (_e != hipSuccess) return hip_fail(_e, where); \
+  } while (0)
+
+}  // namespace
+
+struct sp6_grid_s {
+  sp6_desc desc{};
+  KDims d{};
+  KTab t{};
+  KCoef c{};
+  HostTables h;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  bool coeffs_set = false;
+  double* kappa = nullptr;
+  double* sigma = nullptr;
+  double* eta = nullptr;
+  double* g_in = nullptr;
+  double* g_out = nullptr;
+  // scratch (allocated on first use)
+  double* T = nullptr;
+  double* Ybuf = nullptr;
+  double* acc = nullptr;
+  double* Y2 = nullptr;
+  double* Y3 = nullptr;
+  double* Y4 = nullptr;
+  double* KB = nullptr;
+  double* LACC = nullptr;
+  double* diag_partial = nullptr;
+  double* diag_out = nullptr;
+  float* Yf = nullptr;
+  float* Tf = nullptr;
+
+  hipError_t alloc(void** p, size_t n) {
+    hipError_t e = hipMalloc(p, n);
+    if (e == hipSuccess) {
+      allocs.push_back(*p);
+      bytes += n;
+    }
+    return e;
+  }
+};
+
+namespace {
+
+template <typename T>
+hipError_t upload(sp6_grid g, const std::vector<T>& v, const T** out) {
+  void* p = nullptr;
+  const size_t n = (v.empty() ? 1 : v.size()) * sizeof(T);
+  hipError_t e = g->alloc(&p, n);
+  if (e != hipSuccess) return e;
+  if (!v.empty()) {
+    e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, g->stream);
+    if (e != hipSuccess) return e;
+  }
+  *out = static_cast<const T*>(p);
+  return hipSuccess;
+}
+
+size_t state_bytes(const sp6_grid g) { return size_t(g->d.P) * sizeof(double); }
+
+sp6_status check_grid(sp6_grid g) {
+  if (!g) return fail(SP6_ERR_ARG, "grid handle is NULL");
+  return SP6_OK;
+}
+
+// A device array of `bytes` bytes: non-null, 16-byte aligned, device memory.
+sp6_status check_dev(const void* p, size_t bytes, const char* name) {
+  if (!p) return fail(SP6_ERR_ARG, std::string(name) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(SP6_ERR_ARG, std::string(name) + " is not 16-byte aligned");
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SP6_ERR_ARG, std::string(name) + " is not a device pointer");
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged && attr.type != hipMemoryTypeUnified)
+    return fail(SP6_ERR_ARG, std::string(name) + " is not device memory");
+  (void)bytes;
+  return SP6_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + nb && y < x + na;
+}
+
+sp6_status check_distinct(const void* a, const char* na, const void* b, const char* nb, size_t bytes_a,
+                          size_t bytes_b) {
+  if (a && b && overlap(a, bytes_a, b, bytes_b))
+    return fail(SP6_ERR_ARG, std::string(na) + " and " + nb + " overlap");
+  return SP6_OK;
+}
+
+// Optional per-launch timing: an event before the first launch and after every
+// launch, all on the handle's stream; launch i of kernel class cls[i] spans
+// events i and i + 1.
+struct Timer {
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cls;
+  hipError_t mark(hipStream_t s, int c) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    ev.push_back(e);
+    if (c >= 0) cls.push_back(c);
+    return hipEventRecord(e, s);
+  }
+  ~Timer() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+enum { KC_PHI = 0, KC_THETA = 1, KC_RADIAL = 2, KC_PLANE = 3, KC_FILTER = 4, KC_COUNT = 5 };
+
+hipError_t ensure(sp6_grid g, double** p, size_t n) {
+  if (*p) return hipSuccess;
+  return g->alloc(reinterpret_cast<void**>(p), n);
+}
+
+hipError_t ensure_step_scratch(sp6_grid g) {
+  hipError_t e = ensure(g, &g->T, state_bytes(g));
+  if (e == hipSuccess) e = ensure(g, &g->Ybuf, state_bytes(g));
+  if (e == hipSuccess) e = ensure(g, &g->acc, state_bytes(g));
+  return e;
+}
+
+// the r, theta and phi terms of L Y (or of L^T for the transposed passes) into T
+hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transpose, bool mask_in,
+                        double in_scale, bool* wrote, Timer* tm = nullptr) {
+  hipError_t e = hipSuccess;
+  bool acc = false;
+  const double sg = transpose ? -1.0 : 1.0;
+  if (terms & 4u) {
+    e = launch_phi(g->d, g->t, Y, g->T, acc, sg, mask_in, in_scale, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_PHI);
+    if (e != hipSuccess) return e;
+    acc = true;
+  }
+  if (terms & 2u) {
+    e = launch_theta(g->d, g->t, Y, g->T, acc, sg, mask_in, in_scale, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_THETA);
+    if (e != hipSuccess) return e;
+    acc = true;
+  }
+  if (terms & 1u) {
+    e = launch_radial(g->d, g->t, Y, g->T, acc, transpose, mask_in, in_scale, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_RADIAL);
+    if (e != hipSuccess) return e;
+    acc = true;
+  }
+  *wrote = acc;
+  return e;
+}
+
+sp6_status fp64_rhs_like(sp6_grid g, const double* F, double* out, int mode, uint32_t terms) {
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(ensure(g, &g->T, state_bytes(g)), "allocate scratch");
+  bool wrote = false;
+  HIP_TRY(column_terms(g, F, terms, false, false, 1.0, &wrote), "column passes");
+  StageArgs a{};
+  a.mode = mode;
+  a.Yin = F;
+  a.T = wrote ? g->T : nullptr;
+  a.out = out;
+  a.terms = terms;
+  HIP_TRY(launch_plane(g->d, g->t, g->c, a, g->stream), "plane pass");
+  return SP6_OK;
+}
+
+sp6_status check_state_io(sp6_grid g, const void* in, const char* nin, const void* out, const char* nout) {
+  const size_t B = state_bytes(g);
+  sp6_status s = check_dev(in, B, nin);
+  if (s) return s;
+  s = check_dev(out, B, nout);
+  if (s) return s;
+  return check_distinct(in, nin, out, nout, B, B);
+}
+
+sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm);
+
+}  // namespace
+
+extern "C" {
+
+const char* sp6_last_error(void) { return g_err.c_str(); }
+
+sp6_status sp6_validate_desc(const sp6_desc* desc) {
+  if (!desc) return fail(SP6_ERR_ARG, "desc is NULL");
+  sp6_status code;
+  std::string m = validate_desc(*desc, &code);
+  if (code != SP6_OK) return fail(code, m);
+  return SP6_OK;
+}
+
+sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
+  if (!out) return fail(SP6_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  sp6_status st = sp6_validate_desc(desc);
+  if (st) return st;
+  sp6_grid g = nullptr;
+  try {
+    g = new sp6_grid_s();
+    g->desc = *desc;
+    build_host_tables(*desc, g->h);
+  } catch (...) {
+    delete g;
+    return fail(SP6_ERR_ALLOC, "host allocation failed");
+  }
+  g->stream = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipGetDevice(&g->device);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "hipGetDevice");
+  }
+  KDims& d = g->d;
+  d.n_eps = desc->n_eps;
+  d.n_r = desc->n_r;
+  d.n_th = desc->n_theta;
+  d.n_ph = desc->n_phi;
+  d.n_Th = desc->n_Theta;
+  d.n_Ph = desc->n_Phi;
+  d.plane = d.n_Th * d.n_Ph;
+  d.M = int64_t(d.n_th) * d.n_ph * d.plane;
+  d.P = d.M * d.n_r * d.n_eps;
+  d.nplanes = int64_t(d.n_eps) * d.n_r * d.n_th * d.n_ph;
+  d.bc = desc->bc;
+  d.scattering = desc->scattering;
+
+  const HostTables& h = g->h;
+  KTab& t = g->t;
+#define UP(field) \
+  if ((e = upload(g, h.field, &t.field)) != hipSuccess) goto fail_hip;
+  UP(inv_r) UP(inv_sin_th) UP(cot_th) UP(sin_Th) UP(cos_Th) UP(sin_Ph) UP(cos_Ph) UP(wmean) UP(wflux)
+  UP(eo_th) UP(eo_ph) UP(eo_pl) UP(fl_th) UP(fl_ph) UP(fl_pl) UP(Dpad) UP(DpadT) UP(qN) UP(qJ)
+#undef UP
+  t.KP = h.KP;
+  t.NRP = h.NRP;
+  {
+    const size_t cb = size_t(d.nplanes) * sizeof(double);
+    const size_t gb = size_t(d.n_eps) * d.M * sizeof(double);
+    if ((e = g->alloc(reinterpret_cast<void**>(&g->kappa), cb)) != hipSuccess) goto fail_hip;
+    if ((e = g->alloc(reinterpret_cast<void**>(&g->sigma), cb)) != hipSuccess) goto fail_hip;
+    if ((e = g->alloc(reinterpret_cast<void**>(&g->eta), cb)) != hipSuccess) goto fail_hip;
+    if ((e = g->alloc(reinterpret_cast<void**>(&g->g_in), gb)) != hipSuccess) goto fail_hip;
+    if ((e = g->alloc(reinterpret_cast<void**>(&g->g_out), gb)) != hipSuccess) goto fail_hip;
+    if ((e = hipMemsetAsync(g->g_in, 0, gb, g->stream)) != hipSuccess) goto fail_hip;
+    if ((e = hipMemsetAsync(g->g_out, 0, gb, g->stream)) != hipSuccess) goto fail_hip;
+    if ((e = g->alloc(reinterpret_cast<void**>(&g->diag_partial), diag_partial_count(d) * sizeof(double))) != hipSuccess)
+      goto fail_hip;
+    if ((e = g->alloc(reinterpret_cast<void**>(&g->diag_out), size_t(3) * d.n_eps * sizeof(double))) != hipSuccess)
+      goto fail_hip;
+  }
+  g->c.kappa = g->kappa;
+  g->c.sigma = g->sigma;
+  g->c.eta = g->eta;
+  g->c.g_in = g->g_in;
+  g->c.g_out = g->g_out;
+  // host tables must stay alive until the copies are done
+  if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) goto fail_hip;
+  *out = g;
+  return SP6_OK;
+fail_hip : {
+  sp6_status s = (e == hipErrorOutOfMemory) ? fail(SP6_ERR_ALLOC, "device allocation failed") : hip_fail(e, "sp6_create");
+  (void)hipStreamSynchronize(g->stream);
+  for (void* p : g->allocs) (void)hipFree(p);
+  delete g;
+  return s;
+}
+}
+
+void sp6_destroy(sp6_grid g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  (void)hipStreamSynchronize(g->stream);
+  for (void* p : g->allocs) (void)hipFree(p);
+  delete g;
+}
+
+sp6_status sp6_set_stream(sp6_grid g, void* hip_stream) {
+  if (sp6_status s = check_grid(g)) return s;
+  g->stream = static_cast<hipStream_t>(hip_stream);
+  return SP6_OK;
+}
+
+sp6_status sp6_get_nodes(sp6_grid g, double* r, double* theta, double* phi, double* Theta, double* Phi) {
+  if (sp6_status s = check_grid(g)) return s;
+  const HostTables& h = g->h;
+  if (r) std::memcpy(r, h.r.data(), h.r.size() * sizeof(double));
+  if (theta) std::memcpy(theta, h.theta.data(), h.theta.size() * sizeof(double));
+  if (phi) std::memcpy(phi, h.phi.data(), h.phi.size() * sizeof(double));
+  if (Theta) std::memcpy(Theta, h.Theta.data(), h.Theta.size() * sizeof(double));
+  if (Phi) std::memcpy(Phi, h.Phi.data(), h.Phi.size() * sizeof(double));
+  return SP6_OK;
+}
+
+sp6_status sp6_get_weights(sp6_grid g, double* w_r, double* w_theta, double* w_phi, double* w_Theta,
+                           double* w_Phi) {
+  if (sp6_status s = check_grid(g)) return s;
+  const HostTables& h = g->h;
+  if (w_r) std::memcpy(w_r, h.w_r.data(), h.w_r.size() * sizeof(double));
+  if (w_theta) std::memcpy(w_theta, h.w_th.data(), h.w_th.size() * sizeof(double));
+  if (w_phi) std::memcpy(w_phi, h.w_ph.data(), h.w_ph.size() * sizeof(double));
+  if (w_Theta) std::memcpy(w_Theta, h.w_Th.data(), h.w_Th.size() * sizeof(double));
+  if (w_Phi) std::memcpy(w_Phi, h.w_Ph.data(), h.w_Ph.size() * sizeof(double));
+  return SP6_OK;
+}
+
+sp6_status sp6_set_coefficients(sp6_grid g, const double* kappa, const double* sigma, const double* eta) {
+  if (sp6_status s = check_grid(g)) return s;
+  const size_t cb = size_t(g->d.nplanes) * sizeof(double);
+  if (sp6_status s = check_dev(kappa, cb, "kappa")) return s;
+  if (sp6_status s = check_dev(sigma, cb, "sigma")) return s;
+  if (sp6_status s = check_dev(eta, cb, "eta")) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(hipMemcpyAsync(g->kappa, kappa, cb, hipMemcpyDeviceToDevice, g->stream), "copy kappa");
+  HIP_TRY(hipMemcpyAsync(g->sigma, sigma, cb, hipMemcpyDeviceToDevice, g->stream), "copy sigma");
+  HIP_TRY(hipMemcpyAsync(g->eta, eta, cb, hipMemcpyDeviceToDevice, g->stream), "copy eta");
+  g->coeffs_set = true;
+  return SP6_OK;
+}
+
+sp6_status sp6_set_inflow(sp6_grid g, const double* g_in, const double* g_out) {
+  if (sp6_status s = check_grid(g)) return s;
+  const size_t gb = size_t(g->d.n_eps) * g->d.M * sizeof(double);
+  if (g_in)
+    if (sp6_status s = check_dev(g_in, gb, "g_in")) return s;
+  if (g_out)
+    if (sp6_status s = check_dev(g_out, gb, "g_out")) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  if (g_in)
+    HIP_TRY(hipMemcpyAsync(g->g_in, g_in, gb, hipMemcpyDeviceToDevice, g->stream), "copy g_in");
+  else
+    HIP_TRY(hipMemsetAsync(g->g_in, 0, gb, g->stream), "clear g_in");
+  if (g_out)
+    HIP_TRY(hipMemcpyAsync(g->g_out, g_out, gb, hipMemcpyDeviceToDevice, g->stream), "copy g_out");
+  else
+    HIP_TRY(hipMemsetAsync(g->g_out, 0, gb, g->stream), "clear g_out");
+  return SP6_OK;
+}
+
+sp6_status sp6_project_inflow(sp6_grid g, double* F) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(launch_project(g->d, g->t, g->c, F, g->stream), "project inflow");
+  return SP6_OK;
+}
+
+sp6_status sp6_apply_L_terms(sp6_grid g, uint32_t term_mask, const double* F, double* out) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (term_mask == 0 || term_mask > 31u) return fail(SP6_ERR_ARG, "term_mask must be in [1, 31]");
+  if (sp6_status s = check_state_io(g, F, "F", out, "out")) return s;
+  return fp64_rhs_like(g, F, out, PM_APPLY, term_mask);
+}
+
+sp6_status sp6_apply_L(sp6_grid g, const double* F, double* LF) { return sp6_apply_L_terms(g, 31u, F, LF); }
+
+sp6_status sp6_apply_LT(sp6_grid g, const double* G, double* out) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "apply_LT is FP64-only");
+  if (sp6_status s = check_state_io(g, G, "G", out, "out")) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(ensure(g, &g->T, state_bytes(g)), "allocate scratch");
+  bool wrote = false;
+  HIP_TRY(column_terms(g, G, 7u, true, false, 1.0, &wrote), "transposed column passes");
+  HIP_TRY(launch_plane_LT(g->d, g->t, G, g->T, out, g->stream), "transposed plane pass");
+  return SP6_OK;
+}
+
+sp6_status sp6_rhs(sp6_grid g, const double* F, double* out) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
+  if (sp6_status s = check_state_io(g, F, "F", out, "out")) return s;
+  return fp64_rhs_like(g, F, out, PM_RHS, 31u);
+}
+
+sp6_status sp6_apply_filter(sp6_grid g, double* F) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(launch_filter(g->d, g->t, F, g->stream), "filter");
+  return SP6_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
+  if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
+  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  if (nsteps == 0) return SP6_OK;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(ensure_step_scratch(g), "allocate scratch");
+  const KDims& d = g->d;
+  if (tm) HIP_TRY(tm->mark(g->stream, -1), "event");
+  for (int32_t n = 0; n < nsteps; ++n) {
+    for (int s = 1; s <= 4; ++s) {
+      const double* Yin = (s == 1) ? F : g->Ybuf;
+      bool wrote = false;
+      HIP_TRY(column_terms(g, Yin, 7u, false, false, 1.0, &wrote, tm), "column passes");
+      StageArgs a{};
+      a.mode = PM_STAGE;
+      a.Yin = Yin;
+      a.T = g->T;
+      a.terms = 31u;
+      switch (s) {
+        case 1:
+          a.accsrc = nullptr, a.accdst = g->acc, a.cb = dt / 6.0;
+          a.ysrc = nullptr, a.ynext = g->Ybuf, a.cn = 0.5 * dt;
+          break;
+        case 2:
+          a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
+          a.ysrc = F, a.ynext = g->Ybuf, a.cn = 0.5 * dt;
+          break;
+        case 3:
+          a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
+          a.ysrc = F, a.ynext = g->Ybuf, a.cn = dt;
+          break;
+        default:
+          a.accsrc = g->acc, a.accdst = F, a.cb = dt / 6.0;
+          a.ysrc = nullptr, a.ynext = nullptr, a.cn = 0.0;
+          break;
+      }
+      HIP_TRY(launch_plane(d, g->t, g->c, a, g->stream), "plane pass");
+      if (tm) HIP_TRY(tm->mark(g->stream, KC_PLANE), "event");
+    }
+    if (g->desc.filter) {
+      HIP_TRY(launch_filter(d, g->t, F, g->stream), "filter");
+      if (tm) HIP_TRY(tm->mark(g->stream, KC_FILTER), "event");
+    }
+  }
+  return SP6_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sp6_status sp6_step(sp6_grid g, double* F, double dt, int32_t nsteps) { return run_steps(g, F, dt, nsteps, nullptr); }
+
+sp6_status sp6_step_timed(sp6_grid g, double* F, double dt, int32_t nsteps, double* kernel_ms, int64_t* launches) {
+  if (!kernel_ms || !launches) return fail(SP6_ERR_ARG, "kernel_ms and launches must not be NULL");
+  Timer tm;
+  sp6_status st = run_steps(g, F, dt, nsteps, &tm);
+  if (st) return st;
+  for (int c = 0; c < KC_COUNT; ++c) {
+    kernel_ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  if (tm.ev.empty()) return SP6_OK;
+  HIP_TRY(hipEventSynchronize(tm.ev.back()), "event synchronize");
+  for (size_t i = 0; i < tm.cls.size(); ++i) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, tm.ev[i], tm.ev[i + 1]), "event elapsed");
+    kernel_ms[tm.cls[i]] += ms;
+    launches[tm.cls[i]] += 1;
+  }
+  return SP6_OK;
+}
+
+sp6_status sp6_adjoint_step(sp6_grid g, const double* Fn, double dt, double* lam, double* gk, double* ge,
+                            double* gs) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "adjoint_step is FP64-only");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
+  if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
+  if (sp6_status s = check_state_io(g, Fn, "F_n", lam, "lam")) return s;
+  const size_t cb = size_t(g->d.nplanes) * sizeof(double);
+  double* gr[3] = {gk, ge, gs};
+  const char* gn[3] = {"grad_kappa", "grad_eta", "grad_sigma"};
+  for (int i = 0; i < 3; ++i) {
+    if (!gr[i]) continue;
+    if (sp6_status s = check_dev(gr[i], cb, gn[i])) return s;
+    if (sp6_status s = check_distinct(gr[i], gn[i], Fn, "F_n", cb, state_bytes(g))) return s;
+    if (sp6_status s = check_distinct(gr[i], gn[i], lam, "lam", cb, state_bytes(g))) return s;
+    for (int j = 0; j < i; ++j)
+      if (sp6_status s = check_distinct(gr[i], gn[i], gr[j], gn[j], cb, cb)) return s;
+  }
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  const size_t B = state_bytes(g);
+  HIP_TRY(ensure(g, &g->T, B), "allocate scratch");
+  HIP_TRY(ensure(g, &g->Y2, B), "allocate scratch");
+  HIP_TRY(ensure(g, &g->Y3, B), "allocate scratch");
+  HIP_TRY(ensure(g, &g->Y4, B), "allocate scratch");
+  HIP_TRY(ensure(g, &g->KB, B), "allocate scratch");
+  HIP_TRY(ensure(g, &g->LACC, B), "allocate scratch");
+  const KDims& d = g->d;
+  if (g->desc.filter) HIP_TRY(launch_filter(d, g->t, lam, g->stream), "filter of lam");
+  // recompute the stage inputs Y2, Y3, Y4 from F_n
+  double* Ys[5] = {nullptr, const_cast<double*>(Fn), g->Y2, g->Y3, g->Y4};
+  const double cn[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+  for (int s = 1; s <= 3; ++s) {
+    bool wrote = false;
+    HIP_TRY(column_terms(g, Ys[s], 7u, false, false, 1.0, &wrote), "column passes");
+    StageArgs a{};
+    a.mode = PM_STAGE;
+    a.Yin = Ys[s];
+    a.T = g->T;
+    a.terms = 31u;
+    a.ysrc = (s == 1) ? nullptr : Fn;
+    a.ynext = Ys[s + 1];
+    a.cn = cn[s];
+    HIP_TRY(launch_plane(d, g->t, g->c, a, g->stream), "plane pass");
+  }
+  // transposed stages 4, 3, 2, 1
+  for (int s = 4; s >= 1; --s) {
+    const double* x = (s == 4) ? lam : g->KB;
+    const double xs = (s == 4) ? dt / 6.0 : 1.0;
+    bool wrote = false;
+    HIP_TRY(column_terms(g, x, 7u, true, d.bc != 0, xs, &wrote), "transposed column passes");
+    AdjArgs a{};
+    a.x = x;
+    a.xs = xs;
+    a.T = g->T;
+    a.Ys = Ys[s];
+    a.gk = gk;
+    a.ge = ge;
+    a.gs = gs;
+    a.lam_is_x = (s == 4);
+    switch (s) {
+      case 4:
+        a.lam = lam, a.laccsrc = nullptr, a.laccdst = g->LACC, a.kbnext = g->KB, a.ka = dt / 3.0, a.kb = dt;
+        break;
+      case 3:
+        a.lam = lam, a.laccsrc = g->LACC, a.laccdst = g->LACC, a.kbnext = g->KB, a.ka = dt / 3.0, a.kb = 0.5 * dt;
+        break;
+      case 2:
+        a.lam = lam, a.laccsrc = g->LACC, a.laccdst = g->LACC, a.kbnext = g->KB, a.ka = dt / 6.0, a.kb = 0.5 * dt;
+        break;
+      default:
+        a.lam = nullptr, a.laccsrc = g->LACC, a.laccdst = lam, a.kbnext = nullptr;
+        break;
+    }
+    HIP_TRY(launch_plane_adj(d, g->t, g->c, a, g->stream), "transposed plane pass");
+  }
+  return SP6_OK;
+}
+
+sp6_status sp6_diagnostics(sp6_grid g, const double* F, double* N, double* J_in, double* J_out) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  const double rin = g->h.r.front(), rout = g->h.r.back();
+  HIP_TRY(launch_diag(g->d, g->t, F, g->diag_partial, rin * rin, rout * rout, g->diag_out, g->stream), "diagnostics");
+  std::vector<double> host(size_t(3) * g->d.n_eps);
+  HIP_TRY(hipMemcpyAsync(host.data(), g->diag_out, host.size() * sizeof(double), hipMemcpyDeviceToHost, g->stream),
+          "copy diagnostics");
+  HIP_TRY(hipStreamSynchronize(g->stream), "synchronize");
+  for (int e = 0; e < g->d.n_eps; ++e) {
+    if (N) N[e] = host[3 * e];
+    if (J_in) J_in[e] = host[3 * e + 1];
+    if (J_out) J_out[e] = host[3 * e + 2];
+  }
+  return SP6_OK;
+}
+
+sp6_status sp6_outgoing_flux(sp6_grid g, const double* F, double* j) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  const size_t jb = size_t(g->d.n_eps) * g->d.n_th * g->d.n_ph * sizeof(double);
+  if (sp6_status s = check_dev(j, jb, "j")) return s;
+  if (sp6_status s = check_distinct(F, "F", j, "j", state_bytes(g), jb)) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(launch_outflux(g->d, g->t, F, j, g->stream), "outgoing flux");
+  return SP6_OK;
+}
+
+sp6_status sp6_device_bytes(sp6_grid g, size_t* bytes) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (!bytes) return fail(SP6_ERR_ARG, "bytes is NULL");
+  *bytes = g->bytes;
+  return SP6_OK;
+}
+
+}  // extern "C"

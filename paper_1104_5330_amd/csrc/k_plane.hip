@@ -1,0 +1,418 @@
+// Plane passes: everything that needs a whole (Theta, Phi) plane.
+//
+// A workgroup stages NPW planes in LDS.  Each lane of a wavefront owns one line
+// of length L = 2 n_Theta = n_Phi: either a Theta DFS line (column Phi_m followed
+// by the reversed column Phi_m + pi, since the direction (-Theta, Phi) is
+// (Theta, Phi + pi)) or a Phi row; the wavefronts split the output pairs of every
+// line.  Forward (Eq. Liouvsph): Theta term -(sin Theta / r) dF/dTheta, Phi term
+// -(sin Theta sin Phi cos theta / (r sin theta)) dF/dPhi.  The epilogue adds the
+// r/theta/phi terms produced by the column passes, the collision term
+// eta - (kappa + sigma) F + sigma <F> (Eq. Transp with an isotropic kernel,
+// <F> with Fejer weights in cos Theta), the inflow mask (Sect. 4.2) and the RK4
+// stage update, all in FP64.
+#include "k_common.h"
+
+namespace {
+
+template <int NT>
+struct PC {
+  static constexpr int L = 2 * NT;        // line length (Theta DFS line, Phi row)
+  static constexpr int NF = 2 * NT;       // n_Phi
+  static constexpr int PLANE = NT * NF;
+  static constexpr int LPP = 2 * NT;      // lines per plane
+  static constexpr int NPW = 64 / LPP;    // planes per workgroup
+  static constexpr int NW = NT >= 4 ? 4 : NT;  // wavefronts; each computes PPW output pairs
+  static constexpr int PPW = NT / NW;
+  static constexpr int PTS = NPW * PLANE;  // points per workgroup (64 NT)
+  static constexpr int NTHR = 64 * NW;
+  static constexpr int PPT = PTS / NTHR;   // points per thread in coalesced phases
+  // LDS layout: rows padded by one double so that row-wise (Phi) and column-wise
+  // (Theta) line reads both spread over the banks
+  static constexpr int RS = NF + 1;
+  static constexpr int PS = NT * RS;
+  static constexpr int PTSP = NPW * PS;
+  static SP6_DEV int lds(int p) {
+    const int pl = p / PLANE, r = p % PLANE;
+    return pl * PS + (r / NF) * RS + (r % NF);
+  }
+};
+
+struct PlaneIdx {
+  int e, j, l, k;
+};
+
+SP6_DEV PlaneIdx plane_index(const KDims& d, int64_t pid) {
+  PlaneIdx p;
+  p.k = int(pid % d.n_ph);
+  int64_t q = pid / d.n_ph;
+  p.l = int(q % d.n_th);
+  q /= d.n_th;
+  p.j = int(q % d.n_r);
+  p.e = int(q / d.n_r);
+  return p;
+}
+
+// LDS index of element q of a lane's line
+template <int NT>
+struct LineMap {
+  int b1, s1, b2, s2;
+  SP6_DEV int idx(int q) const { return q < NT ? b1 + q * s1 : b2 + (2 * NT - 1 - q) * s2; }
+};
+
+template <int NT>
+SP6_DEV LineMap<NT> line_map(int pl, int li) {
+  using C = PC<NT>;
+  LineMap<NT> m;
+  if (li < NT) {  // Theta DFS line for Phi column li and its partner li + NT
+    m.b1 = pl * C::PS + li;
+    m.s1 = C::RS;
+    m.b2 = pl * C::PS + li + NT;
+    m.s2 = C::RS;
+  } else {  // Phi row i = li - NT
+    const int i = li - NT;
+    m.b1 = pl * C::PS + i * C::RS;
+    m.s1 = 1;
+    m.b2 = pl * C::PS + i * C::RS + (C::L - 1);
+    m.s2 = -1;
+  }
+  return m;
+}
+
+// Forward coefficient of line element q (including the DFS partner sign for the
+// Theta line: the partner derivative is -z).
+template <int NT>
+SP6_DEV double line_coef(bool isTh, int q, int li, double inv_r, double cot_th, const double* sTh,
+                         const double* sPh) {
+  if (isTh) {
+    const int iTh = q < NT ? q : 2 * NT - 1 - q;
+    const double sg = q < NT ? -1.0 : 1.0;
+    return sg * sTh[iTh] * inv_r;
+  }
+  const int i = li - NT;
+  return -sTh[i] * sPh[q] * cot_th * inv_r;
+}
+
+// ---------------------------------------------------------------------------
+// forward: L F (partial), right-hand side, or one RK4 stage
+
+template <int NT>
+__global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a) {
+  using C = PC<NT>;
+  __shared__ double sY[C::PTSP];
+  __shared__ double sR[2][C::PTSP];
+  __shared__ double sMean[C::NPW * NT];
+  __shared__ double sTh[NT], sPh[C::NF];
+
+  const int tid = threadIdx.x;
+  const int64_t plane0 = int64_t(blockIdx.x) * C::NPW;
+  const int64_t gbase = plane0 * C::PLANE;
+  const int64_t npl = d.nplanes;
+  if (tid < NT) sTh[tid] = t.sin_Th[tid];
+  if (tid < C::NF) sPh[tid] = t.sin_Ph[tid];
+
+  double tv[C::PPT], av[C::PPT], yv[C::PPT];
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int p = tid + q * C::NTHR;
+    const bool ok = plane0 + p / C::PLANE < npl;
+    const int64_t gp = gbase + p;
+    sY[C::lds(p)] = ok ? a.Yin[gp] : 0.0;
+    tv[q] = (ok && a.T) ? a.T[gp] : 0.0;
+    av[q] = (ok && a.accsrc) ? a.accsrc[gp] : 0.0;
+    yv[q] = (ok && a.ysrc) ? a.ysrc[gp] : 0.0;
+  }
+  __syncthreads();
+
+  {  // line phase
+    const int lane = tid & 63;
+    const int part = wave_uniform(tid >> 6);
+    const int pl = lane / C::LPP, li = lane % C::LPP;
+    const bool isTh = li < NT;
+    const LineMap<NT> lm = line_map<NT>(pl, li);
+    const int64_t pid = plane0 + pl;
+    const PlaneIdx pi = plane_index(d, pid < npl ? pid : 0);
+    const double inv_r = t.inv_r[pi.j], cot_th = t.cot_th[pi.l];
+    double v[C::L];
+#pragma unroll
+    for (int q = 0; q < C::L; ++q) v[q] = sY[lm.idx(q)];
+    if (part == 0 && !isTh) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < C::L; ++q) s += v[q];
+      sMean[pl * NT + (li - NT)] = t.wmean[li - NT] * s;
+    }
+    double* out = sR[isTh ? 0 : 1];
+    eo_split<C::L>(v);
+    eo_pairs<C::L, C::PPW, true>(t.eo_pl, part * C::PPW, v, [&](int q, double z) {
+      out[lm.idx(q)] = line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh) * z;
+    });
+  }
+  __syncthreads();
+
+  const bool useTh = a.terms & 8u, usePh = a.terms & 16u;
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int p = tid + q * C::NTHR;
+    const int pl = p / C::PLANE;
+    const int64_t pid = plane0 + pl;
+    if (pid >= npl) continue;
+    const int64_t gp = gbase + p;
+    const int lp = C::lds(p);
+    double LY = tv[q];
+    if (useTh) LY += sR[0][lp];
+    if (usePh) LY += sR[1][lp];
+    if (a.mode == PM_APPLY) {
+      a.out[gp] = LY;
+      continue;
+    }
+    const int iTh = (p % C::PLANE) / C::NF;
+    const PlaneIdx pi = plane_index(d, pid);
+    const double Yv = sY[lp];
+    const double ka = cf.kappa[pid], et = cf.eta[pid];
+    double k = -LY + et - ka * Yv;
+    if (d.scattering) {
+      const double si = cf.sigma[pid];
+      double mean = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < NT; ++ii) mean += sMean[pl * NT + ii];
+      k += si * (mean - Yv);
+    }
+    if (is_inflow(d, t, pi.j, iTh)) k = 0.0;
+    if (a.mode == PM_RHS) {
+      a.out[gp] = k;
+      continue;
+    }
+    if (a.accdst) a.accdst[gp] = (a.accsrc ? av[q] : Yv) + a.cb * k;
+    if (a.ynext) a.ynext[gp] = (a.ysrc ? yv[q] : Yv) + a.cn * k;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transpose: one adjoint stage, or L^T only (lt_out).
+//   u = M (xs x);  a = -(T + Theta^T + Phi^T) - (kappa + sigma) u + sigma avg^T u
+//   lacc = (laccsrc or lam) + a;  kbnext = ka lam + kb a
+//   per plane: g_kappa -= sum u Y_s, g_eta += sum u, g_sigma += <Y_s> sum u - sum u Y_s
+// Transposed line: v_q = coef_q u_q; z = D v; result_q = -z_q (D^T = -D).
+
+template <int NT>
+__global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCoef cf, AdjArgs a,
+                                                            double* lt_out) {
+  using C = PC<NT>;
+  __shared__ double sU[C::PTSP];
+  __shared__ double sY[C::PTSP];
+  __shared__ double sR[2][C::PTSP];
+  __shared__ double sRed[C::NPW * NT][3];
+  __shared__ double sTh[NT], sPh[C::NF];
+
+  const int tid = threadIdx.x;
+  const int64_t plane0 = int64_t(blockIdx.x) * C::NPW;
+  const int64_t gbase = plane0 * C::PLANE;
+  const int64_t npl = d.nplanes;
+  const bool lt = lt_out != nullptr;
+  const bool grads = !lt && (a.gk || a.ge || a.gs) && a.Ys;
+  if (tid < NT) sTh[tid] = t.sin_Th[tid];
+  if (tid < C::NF) sPh[tid] = t.sin_Ph[tid];
+
+  double xr[C::PPT], tv[C::PPT], lv[C::PPT], cv[C::PPT];
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int p = tid + q * C::NTHR;
+    const int64_t pid = plane0 + p / C::PLANE;
+    const bool ok = pid < npl;
+    const int64_t gp = gbase + p;
+    const double x = ok ? a.x[gp] : 0.0;
+    xr[q] = x;
+    double u = lt ? x : a.xs * x;
+    if (!lt && ok) {
+      const PlaneIdx pi = plane_index(d, pid);
+      if (is_inflow(d, t, pi.j, (p % C::PLANE) / C::NF)) u = 0.0;
+    }
+    sU[C::lds(p)] = u;
+    if (grads) sY[C::lds(p)] = ok ? a.Ys[gp] : 0.0;
+    tv[q] = (ok && a.T) ? a.T[gp] : 0.0;
+    lv[q] = (ok && !lt && !a.lam_is_x && a.lam) ? a.lam[gp] : 0.0;
+    cv[q] = (ok && !lt && a.laccsrc) ? a.laccsrc[gp] : 0.0;
+  }
+  __syncthreads();
+
+  {
+    const int lane = tid & 63;
+    const int part = wave_uniform(tid >> 6);
+    const int pl = lane / C::LPP, li = lane % C::LPP;
+    const bool isTh = li < NT;
+    const LineMap<NT> lm = line_map<NT>(pl, li);
+    const int64_t pid = plane0 + pl;
+    const PlaneIdx pi = plane_index(d, pid < npl ? pid : 0);
+    const double inv_r = t.inv_r[pi.j], cot_th = t.cot_th[pi.l];
+    double v[C::L];
+#pragma unroll
+    for (int q = 0; q < C::L; ++q)
+      v[q] = line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh) * sU[lm.idx(q)];
+    if (part == 0 && !isTh && !lt) {
+      const int i = li - NT;
+      double su = 0.0, suy = 0.0, sy = 0.0;
+      for (int q = 0; q < C::L; ++q) {
+        const int ix = lm.idx(q);
+        su += sU[ix];
+        if (grads) {
+          suy += sU[ix] * sY[ix];
+          sy += sY[ix];
+        }
+      }
+      sRed[pl * NT + i][0] = su;
+      sRed[pl * NT + i][1] = suy;
+      sRed[pl * NT + i][2] = t.wmean[i] * sy;
+    }
+    double* out = sR[isTh ? 0 : 1];
+    eo_split<C::L>(v);
+    eo_pairs<C::L, C::PPW, true>(t.eo_pl, part * C::PPW, v, [&](int q, double z) { out[lm.idx(q)] = -z; });
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int p = tid + q * C::NTHR;
+    const int pl = p / C::PLANE;
+    const int64_t pid = plane0 + pl;
+    if (pid >= npl) continue;
+    const int64_t gp = gbase + p;
+    const int lp = C::lds(p);
+    const double LTu = tv[q] + sR[0][lp] + sR[1][lp];
+    if (lt) {
+      lt_out[gp] = LTu;
+      continue;
+    }
+    const double u = sU[lp];
+    const int iTh = (p % C::PLANE) / C::NF;
+    double av = -LTu - cf.kappa[pid] * u;
+    if (d.scattering) {
+      double su = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < NT; ++ii) su += sRed[pl * NT + ii][0];
+      const double si = cf.sigma[pid];
+      av += si * (t.wmean[iTh] * su - u);
+    }
+    const double lam = a.lam_is_x ? xr[q] : lv[q];
+    if (a.laccdst) a.laccdst[gp] = (a.laccsrc ? cv[q] : lam) + av;
+    if (a.kbnext) a.kbnext[gp] = a.ka * lam + a.kb * av;
+  }
+
+  if (grads && tid < C::NPW) {
+    const int pl = tid;
+    const int64_t pid = plane0 + pl;
+    if (pid < npl) {
+      double su = 0.0, suy = 0.0, my = 0.0;
+      for (int ii = 0; ii < NT; ++ii) {
+        su += sRed[pl * NT + ii][0];
+        suy += sRed[pl * NT + ii][1];
+        my += sRed[pl * NT + ii][2];
+      }
+      if (a.gk) a.gk[pid] -= suy;
+      if (a.ge) a.ge[pid] += su;
+      if (a.gs && d.scattering) a.gs[pid] += my * su - suy;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// filter of the Theta DFS lines, then of the Phi rows (in place)
+
+template <int NT>
+__global__ __launch_bounds__(PC<NT>::NTHR) void k_filter_plane(KDims d, KTab t, double* __restrict__ F) {
+  using C = PC<NT>;
+  __shared__ double sY[C::PTSP];
+  __shared__ double sR[C::PTSP];
+  const int tid = threadIdx.x;
+  const int64_t plane0 = int64_t(blockIdx.x) * C::NPW;
+  const int64_t gbase = plane0 * C::PLANE;
+  const int64_t npl = d.nplanes;
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int p = tid + q * C::NTHR;
+    sY[C::lds(p)] = (plane0 + p / C::PLANE < npl) ? F[gbase + p] : 0.0;
+  }
+  __syncthreads();
+  const int lane = tid & 63;
+  const int part = wave_uniform(tid >> 6);
+  const int pl = lane / C::LPP, li = lane % C::LPP;
+  const bool isTh = li < NT;
+  const LineMap<NT> lm = line_map<NT>(pl, li);
+  if (isTh) {
+    double v[C::L];
+#pragma unroll
+    for (int q = 0; q < C::L; ++q) v[q] = sY[lm.idx(q)];
+    eo_split<C::L>(v);
+    eo_pairs<C::L, C::PPW, false>(t.fl_pl, part * C::PPW, v, [&](int q, double z) { sR[lm.idx(q)] = z; });
+  }
+  __syncthreads();
+  if (!isTh) {
+    double v[C::L];
+#pragma unroll
+    for (int q = 0; q < C::L; ++q) v[q] = sR[lm.idx(q)];
+    eo_split<C::L>(v);
+    eo_pairs<C::L, C::PPW, false>(t.fl_pl, part * C::PPW, v, [&](int q, double z) { sY[lm.idx(q)] = z; });
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const int p = tid + q * C::NTHR;
+    if (plane0 + p / C::PLANE < npl) F[gbase + p] = sY[C::lds(p)];
+  }
+}
+
+template <int NT>
+unsigned plane_blocks(const KDims& d) {
+  return unsigned((d.nplanes + PC<NT>::NPW - 1) / PC<NT>::NPW);
+}
+
+}  // namespace
+
+hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
+  switch (d.n_Th) {
+#define CASE(N) \
+  case N: k_plane<N><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a); break;
+    CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_adj(const KDims& d, const KTab& t, const KCoef& c, const AdjArgs& a, hipStream_t s) {
+  switch (d.n_Th) {
+#define CASE(N) \
+  case N: k_plane_adj<N><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a, nullptr); break;
+    CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_LT(const KDims& d, const KTab& t, const double* G, const double* T, double* out,
+                           hipStream_t s) {
+  AdjArgs a{};
+  a.x = G;
+  a.xs = 1.0;
+  a.T = T;
+  KCoef c{};
+  switch (d.n_Th) {
+#define CASE(N) \
+  case N: k_plane_adj<N><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a, out); break;
+    CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_plane(const KDims& d, const KTab& t, double* F, hipStream_t s) {
+  switch (d.n_Th) {
+#define CASE(N) \
+  case N: k_filter_plane<N><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, F); break;
+    CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}

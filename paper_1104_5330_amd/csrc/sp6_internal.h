@@ -1,0 +1,142 @@
+// Internal declarations shared by the host API and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sp6d.h"
+
+// ---------------------------------------------------------------------------
+// sizes and device tables, passed to kernels by value
+
+struct KDims {
+  int n_eps, n_r, n_th, n_ph, n_Th, n_Ph;
+  int plane;        // n_Th * n_Ph: one (Theta, Phi) plane
+  int64_t M;        // n_th * n_ph * plane: points per (eps, r)
+  int64_t P;        // all points
+  int64_t nplanes;  // n_eps * n_r * n_th * n_ph
+  int bc, scattering;
+};
+
+struct KTab {
+  const double* inv_r;       // [n_r]
+  const double* inv_sin_th;  // [n_th]
+  const double* cot_th;      // [n_th] cos/sin
+  const double* sin_Th;      // [n_Th]
+  const double* cos_Th;      // [n_Th]
+  const double* sin_Ph;      // [n_Ph]
+  const double* cos_Ph;      // [n_Ph]
+  const double* wmean;       // [n_Th]  w_i (2 pi / n_Ph) / (4 pi)
+  const double* wflux;       // [n_Th]  w_i (2 pi / n_Ph) cos(Theta_i) where cos > 0, else 0
+  const double* eo_th;       // even/odd split of the 2 n_th DFS derivative (2 h^2, h = n_th)
+  const double* eo_ph;       // phi line derivative, h = n_ph / 2
+  const double* eo_pl;       // Theta DFS and Phi line derivative, h = n_Th (n_Ph = 2 n_Th)
+  const double* fl_th;       // filter, same layouts
+  const double* fl_ph;
+  const double* fl_pl;
+  const double* Dpad;        // radial matrix, zero padded [NRP][KP]
+  const double* DpadT;       // its transpose, same padding
+  const double* qN;          // [n_r * n_th * n_Th] weights of the particle number
+  const double* qJ;          // [n_th * n_Th] weights of the boundary flux (without r^2)
+  // mixed precision copies
+  const float* eo_th_f;
+  const float* eo_ph_f;
+  const float* eo_pl_f;
+  const float* Dsplit;       // bf16x3 split of Dpad as 3 float planes [3][NRP][KP]
+  int KP, NRP;
+};
+
+struct KCoef {
+  const double* kappa;  // [nplanes]
+  const double* sigma;
+  const double* eta;
+  const double* g_in;   // [n_eps][n_th][n_ph][plane]
+  const double* g_out;
+};
+
+// ---------------------------------------------------------------------------
+// host tables
+
+struct HostTables {
+  std::vector<double> r, theta, phi, Theta, Phi;
+  std::vector<double> w_r, w_th, w_ph, w_Th, w_Ph;
+  std::vector<double> Dr;  // n_r x n_r, row major
+  std::vector<double> inv_r, inv_sin_th, cot_th, sin_Th, cos_Th, sin_Ph, cos_Ph, wmean, wflux;
+  std::vector<double> eo_th, eo_ph, eo_pl, fl_th, fl_ph, fl_pl;
+  std::vector<double> Dpad, DpadT;
+  std::vector<double> qN, qJ;
+  int KP = 0, NRP = 0;
+};
+
+void build_host_tables(const sp6_desc& d, HostTables& t);
+std::string validate_desc(const sp6_desc& d, sp6_status* code);
+
+// ---------------------------------------------------------------------------
+// launchers (defined in the .hip files); all return hipSuccess or an error
+
+enum PlaneMode { PM_APPLY = 0, PM_RHS = 1, PM_STAGE = 2 };
+
+struct StageArgs {
+  int mode;              // PlaneMode
+  const double* Yin;     // stage input (FP64 path)
+  const double* T;       // sum of the r, theta, phi terms of L Yin (may be null = 0)
+  double* out;           // PM_APPLY / PM_RHS output
+  // PM_STAGE: accdst = (acc_from_Y ? Yin : accsrc) + cb * k ; ynext = (ysrc ? ysrc : Yin) + cn * k
+  const double* accsrc;
+  double* accdst;
+  double cb;
+  const double* ysrc;
+  double* ynext;
+  double cn;
+  uint32_t terms;        // bit 3 Theta, bit 4 Phi
+};
+
+hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
+                      double coef_sign, bool mask_in, double in_scale, hipStream_t s);
+hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
+                        double coef_sign, bool mask_in, double in_scale, hipStream_t s);
+hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
+                         bool transpose, bool mask_in, double in_scale, hipStream_t s);
+hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a,
+                        hipStream_t s);
+
+struct AdjArgs {
+  const double* x;       // input (lam or kb), scaled by xs, masked
+  double xs;
+  const double* T;       // transposed r/theta/phi terms of M xs x
+  const double* Ys;      // stage input (for the coefficient gradients), may be null
+  const double* lam;     // dLoss/dF_{n+1} (for kb_next)
+  const double* laccsrc; // null: lacc = lam + a
+  double* laccdst;
+  double* kbnext;        // may be null
+  double ka, kb;         // kbnext = ka * lam + kb * a
+  double* gk;
+  double* ge;
+  double* gs;
+  int lam_is_x;          // x == lam (stage 4): reuse the loaded value
+};
+hipError_t launch_plane_adj(const KDims& d, const KTab& t, const KCoef& c, const AdjArgs& a,
+                            hipStream_t s);
+hipError_t launch_plane_LT(const KDims& d, const KTab& t, const double* G, const double* T,
+                           double* out, hipStream_t s);
+
+// filter, projection, diagnostics
+hipError_t launch_filter(const KDims& d, const KTab& t, double* F, hipStream_t s);
+hipError_t launch_project(const KDims& d, const KTab& t, const KCoef& c, double* F, hipStream_t s);
+hipError_t launch_diag(const KDims& d, const KTab& t, const double* F, double* partial, double r_in2,
+                       double r_out2, double* out3, hipStream_t s);
+size_t diag_partial_count(const KDims& d);
+hipError_t launch_outflux(const KDims& d, const KTab& t, const double* F, double* j, hipStream_t s);
+
+// mixed precision (FP32 stage copies, bf16x3 radial MFMA)
+struct MixedBufs {
+  float* Yf;   // FP32 stage input
+  float* Tf;   // FP32 r/theta/phi terms
+};
+hipError_t launch_mixed_stage(const KDims& d, const KTab& t, const KCoef& c, int stage,
+                              double* y, double* acc, MixedBufs& b, double dt, hipStream_t s);
+hipError_t launch_mixed_apply(const KDims& d, const KTab& t, const KCoef& c, int mode,
+                              const double* F, double* out, MixedBufs& b, hipStream_t s);

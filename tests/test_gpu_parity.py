@@ -1,0 +1,228 @@
+"""GPU parity: every entry point of the HIP library against the FP64 oracle,
+element by element, on seeded inputs that span several tiles and ragged tails.
+Tolerance: 1e-12 normwise relative (FP64 path)."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import ops, step, adjoint, diagnostics
+from tests.gpu_util import need_gpu, maxrel, to_dev, to_host, oracle_grid, small, banner
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+# (name, config) shapes: tiny, ragged (odd n_eps * n_r with the 16-plane kernel),
+# the small workload, a reduced workload-2 shape, one of each line length
+SHAPES = {
+    "tiny": small(3, n_eps=1, n_r=5, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
+    "ragged": small(3, n_eps=3, n_r=7, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
+    "cfg1": small(3, n_eps=1),
+    "w2_reduced": small(3, n_eps=2, n_r=9),
+    "mixed_lines": small(3, n_eps=2, n_r=17, n_theta=4, n_phi=64, n_Theta=8, n_Phi=16),
+    "big_lines": small(3, n_eps=1, n_r=6, n_theta=32, n_phi=8, n_Theta=32, n_Phi=64),
+}
+SHAPES["cfg1"] = synth.config(1).scaled(physics="scatter")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    import paper_1104_5330_amd  # noqa: F401  (fails loudly if the library is missing)
+
+
+def make(cfg, **kw):
+    from paper_1104_5330_amd import Sp6Grid
+    return Sp6Grid.from_config(cfg, **kw)
+
+
+def setup(cfg, seed=0, bc=True, scattering=True):
+    G = make(cfg, bc=bc, scattering=scattering)
+    F = synth.fields.random_state(cfg, seed)
+    k, s, e = synth.fields.random_coeffs(cfg, seed + 1)
+    G.set_coefficients(to_dev(k), to_dev(s), to_dev(e))
+    return G, F, (k, s, e)
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_terms(name):
+    cfg = SHAPES[name]
+    banner(f"terms {name} {cfg.shape}")
+    G, F, _ = setup(cfg)
+    g = oracle_grid(cfg)
+    c_r, c_th, c_ph, c_Th, c_Ph = ops.liouville_coefficients(g)
+    want = {1: c_r * ops.d_r(F, g), 2: c_th * ops.d_theta(F, g), 4: c_ph * ops.d_phi(F, g),
+            8: c_Th * ops.d_Theta(F, g), 16: c_Ph * ops.d_Phi(F, g)}
+    Fd = to_dev(F)
+    errs = {bit: maxrel(to_host(G.apply_L_terms(bit, Fd)), w) for bit, w in want.items()}
+    errs[31] = maxrel(to_host(G.apply_L(Fd)), ops.apply_L(F, g))
+    assert max(errs.values()) <= TOL, (name, errs)
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_rhs_and_transpose(name):
+    cfg = SHAPES[name]
+    banner(f"rhs/LT {name}")
+    G, F, (k, s, e) = setup(cfg, seed=3)
+    g = oracle_grid(cfg)
+    got = to_host(G.rhs(to_dev(F)))
+    assert maxrel(got, ops.rhs(F, g, k, s, e)) <= TOL
+    X = synth.fields.random_state(cfg, 9)
+    got = to_host(G.apply_LT(to_dev(X)))
+    assert maxrel(got, ops.apply_LT(X, g)) <= TOL
+
+
+@pytest.mark.parametrize("bc,scat", [(True, True), (False, False), (True, False)])
+def test_rhs_switches(bc, scat):
+    cfg = SHAPES["w2_reduced"]
+    G, F, (k, s, e) = setup(cfg, seed=4, bc=bc, scattering=scat)
+    g = oracle_grid(cfg)
+    got = to_host(G.rhs(to_dev(F)))
+    assert maxrel(got, ops.rhs(F, g, k, s, e, bc=bc, scattering=scat)) <= TOL
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "big_lines"])
+def test_step(name):
+    cfg = SHAPES[name]
+    banner(f"step {name}")
+    G, F, (k, s, e) = setup(cfg, seed=5)
+    g = oracle_grid(cfg)
+    dt = cfg.dt
+    p = step.Physics(k, s, e, bc=True, scattering=True)
+    want = step.run(F, g, p, dt, 3)
+    Fd = to_dev(F)
+    G.step(Fd, dt, 3)
+    assert maxrel(to_host(Fd), want) <= TOL
+
+
+def test_step_is_deterministic():
+    cfg = SHAPES["w2_reduced"]
+    G, F, _ = setup(cfg, seed=6)
+    a = to_dev(F)
+    b = to_dev(F)
+    G.step(a, cfg.dt, 2)
+    G.step(b, cfg.dt, 2)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced"])
+def test_adjoint_step(name):
+    cfg = SHAPES[name]
+    banner(f"adjoint {name}")
+    G, F, (k, s, e) = setup(cfg, seed=7)
+    g = oracle_grid(cfg)
+    dt = cfg.dt
+    p = step.Physics(k, s, e, bc=True, scattering=True)
+    lam = synth.fields.random_state(cfg, 8)
+    lam_prev, gk, ge, gs = adjoint.adjoint_step(F, lam, g, p, dt)
+    lam_d = to_dev(lam)
+    z = torch.zeros(cfg.shape[:4], dtype=torch.float64, device="cuda")
+    gkd, ged, gsd = z.clone() + 1.0, z.clone(), z.clone()
+    G.adjoint_step(to_dev(F), dt, lam_d, gkd, ged, gsd)
+    assert maxrel(to_host(lam_d), lam_prev) <= TOL
+    assert maxrel(to_host(gkd) - 1.0, gk) <= 1e-11  # accumulated onto 1.0
+    assert maxrel(to_host(ged), ge) <= 1e-11
+    assert maxrel(to_host(gsd), gs) <= 1e-11
+
+
+def test_adjoint_dot_product_gpu():
+    cfg = SHAPES["w2_reduced"]
+    G, F, _ = setup(cfg, seed=10)
+    lam = synth.fields.random_state(cfg, 11)
+    dF = synth.fields.random_state(cfg, 12)
+    dt = cfg.dt
+    Fd = to_dev(F + dF)
+    G.step(Fd, dt, 1)
+    F0 = to_dev(F)
+    G.step(F0, dt, 1)
+    lin = to_host(Fd) - to_host(F0)  # the step is affine in F: exact up to rounding
+    lam_d = to_dev(lam)
+    G.adjoint_step(to_dev(F), dt, lam_d)
+    lhs = float(np.sum(lam * lin))
+    rhs = float(np.sum(to_host(lam_d) * dF))
+    assert lhs == pytest.approx(rhs, rel=1e-10)
+
+
+@pytest.mark.parametrize("name", ["tiny", "cfg1", "big_lines"])
+def test_filter(name):
+    cfg = SHAPES[name]
+    G, F, _ = setup(cfg, seed=13)
+    g = oracle_grid(cfg)
+    Fd = to_dev(F)
+    G.apply_filter(Fd)
+    assert maxrel(to_host(Fd), ops.apply_filter(F, g)) <= TOL
+
+
+def test_step_with_filter():
+    cfg = SHAPES["cfg1"]
+    G = make(cfg, filter=True)
+    F = synth.fields.beam(cfg)
+    k, s, e = synth.fields.random_coeffs(cfg, 2)
+    G.set_coefficients(to_dev(k), to_dev(s), to_dev(e))
+    g = oracle_grid(cfg)
+    p = step.Physics(k, s, e, filt=True)
+    want = step.run(F, g, p, cfg.dt, 2)
+    Fd = to_dev(F)
+    G.step(Fd, cfg.dt, 2)
+    assert maxrel(to_host(Fd), want) <= TOL
+    lam = synth.fields.random_state(cfg, 3)
+    lp, gk, ge, gs = adjoint.adjoint_step(F, lam, g, p, cfg.dt)
+    ld = to_dev(lam)
+    G.adjoint_step(to_dev(F), cfg.dt, ld)
+    assert maxrel(to_host(ld), lp) <= TOL
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced"])
+def test_diagnostics_and_flux(name):
+    cfg = SHAPES[name]
+    G, F, _ = setup(cfg, seed=14)
+    g = oracle_grid(cfg)
+    N, Ji, Jo = G.diagnostics(to_dev(F))
+    wN, wJi, wJo = diagnostics.fluxes(F, g)
+    scale = np.max(np.abs(wN)) + np.max(np.abs(wJi)) + np.max(np.abs(wJo))
+    assert np.max(np.abs(N - wN)) <= 1e-13 * scale
+    assert np.max(np.abs(Ji - wJi)) <= 1e-13 * scale
+    assert np.max(np.abs(Jo - wJo)) <= 1e-13 * scale
+    j = to_host(G.outgoing_flux(to_dev(F)))
+    assert maxrel(j, diagnostics.outgoing_flux_map(F, g)) <= 1e-13
+
+
+def test_inflow_projection_and_hold():
+    cfg = SHAPES["w2_reduced"]
+    G, F, (k, s, e) = setup(cfg, seed=15)
+    gi, go = synth.fields.inflow_planes(cfg, 16)
+    G.set_inflow(to_dev(gi), to_dev(go))
+    g = oracle_grid(cfg)
+    want = ops.project_inflow(F, g, gi, go)
+    Fd = to_dev(F)
+    G.project_inflow(Fd)
+    assert np.array_equal(to_host(Fd), want)
+    # the inflow values are held by the step
+    p = step.Physics(k, s, e)
+    want = step.run(want, g, p, cfg.dt, 2)
+    G.step(Fd, cfg.dt, 2)
+    got = to_host(Fd)
+    assert maxrel(got, want) <= TOL
+    cT = np.cos(g.Theta)
+    assert np.array_equal(got[:, 0][:, :, :, cT > 0], gi[:, :, :, cT > 0])
+    G.set_inflow(None, None)
+    Fd = to_dev(F)
+    G.project_inflow(Fd)
+    assert np.all(to_host(Fd)[:, 0][:, :, :, cT > 0] == 0.0)
+
+
+def test_config1_free_streaming_closed_form():
+    # vacuum, zero inflow, 10 steps (report only: resolution limited)
+    cfg = synth.config(1)
+    G = make(cfg, scattering=False)
+    z = torch.zeros(cfg.shape[:4], dtype=torch.float64, device="cuda")
+    G.set_coefficients(z, z, z)
+    F = synth.fields.beam(cfg)
+    g = oracle_grid(cfg)
+    F = ops.project_inflow(F, g)
+    Fd = to_dev(F)
+    G.step(Fd, cfg.dt, cfg.steps)
+    want = step.run(F, g, step.Physics.vacuum(g), cfg.dt, cfg.steps)
+    assert maxrel(to_host(Fd), want) <= TOL

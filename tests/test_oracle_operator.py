@@ -297,3 +297,17 @@ def test_rhs_at_matches_full(g1):
         assert ops.rhs_at(F, g, kappa, sigma, eta, idx) == pytest.approx(full[idx], rel=1e-12, abs=1e-12)
     for idx in [(0, 0, 0, 0, 0, 0), (1, 8, 3, 7, 3, 7), (0, 0, 1, 2, 3, 4)]:
         assert ops.rhs_at(F, g, kappa, sigma, eta, idx) == pytest.approx(full[idx], rel=1e-12, abs=1e-12)
+
+
+def test_project_inflow_sets_only_incoming_half():
+    g = og.make_grid(2, 5, 2, 4, 4, 8)
+    rng = np.random.default_rng(0)
+    F = rng.normal(size=g.shape)
+    gi = rng.normal(size=(2, 2, 4, 4, 8))
+    go = rng.normal(size=(2, 2, 4, 4, 8))
+    P = ops.project_inflow(F, g, gi, go)
+    cT = np.cos(g.Theta)
+    for i in range(g.n_Theta):
+        np.testing.assert_array_equal(P[:, 0, :, :, i], gi[:, :, :, i] if cT[i] > 0 else F[:, 0, :, :, i])
+        np.testing.assert_array_equal(P[:, -1, :, :, i], go[:, :, :, i] if cT[i] < 0 else F[:, -1, :, :, i])
+    np.testing.assert_array_equal(P[:, 1:-1], F[:, 1:-1])
