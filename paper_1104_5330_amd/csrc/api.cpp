@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -230,6 +232,20 @@ sp6_status sp6_validate_desc(const sp6_desc* desc) {
   return SP6_OK;
 }
 
+// The line-operator tables live in constant memory, one copy per device and
+// kernel file; they are written once per device per process.
+static hipError_t init_device_tables(int device) {
+  static std::mutex mu;
+  static std::set<int> done;
+  std::lock_guard<std::mutex> lock(mu);
+  if (done.count(device)) return hipSuccess;
+  const std::vector<double> tab = build_line_tables();
+  hipError_t e = init_line_tables_columns(tab.data());
+  if (e == hipSuccess) e = init_line_tables_plane(tab.data());
+  if (e == hipSuccess) done.insert(device);
+  return e;
+}
+
 sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
   if (!out) return fail(SP6_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -250,6 +266,11 @@ sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
     delete g;
     return hip_fail(e, "hipGetDevice");
   }
+  e = init_device_tables(g->device);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "copy line tables");
+  }
   KDims& d = g->d;
   d.n_eps = desc->n_eps;
   d.n_r = desc->n_r;
@@ -263,13 +284,18 @@ sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
   d.nplanes = int64_t(d.n_eps) * d.n_r * d.n_th * d.n_ph;
   d.bc = desc->bc;
   d.scattering = desc->scattering;
+  if ((e = hipDeviceGetAttribute(&d.ncu, hipDeviceAttributeMultiprocessorCount, g->device)) != hipSuccess) {
+    delete g;
+    return hip_fail(e, "hipDeviceGetAttribute");
+  }
+  if (d.ncu < 1) d.ncu = 1;
 
   const HostTables& h = g->h;
   KTab& t = g->t;
 #define UP(field) \
   if ((e = upload(g, h.field, &t.field)) != hipSuccess) goto fail_hip;
   UP(inv_r) UP(inv_sin_th) UP(cot_th) UP(sin_Th) UP(cos_Th) UP(sin_Ph) UP(cos_Ph) UP(wmean) UP(wflux)
-  UP(eo_th) UP(eo_ph) UP(eo_pl) UP(fl_th) UP(fl_ph) UP(fl_pl) UP(Dpad) UP(DpadT) UP(qN) UP(qJ)
+  UP(Dpad) UP(DpadT) UP(qN) UP(qJ)
 #undef UP
   t.KP = h.KP;
   t.NRP = h.NRP;

@@ -23,13 +23,20 @@ namespace {
 
 constexpr int CB = 256;  // threads per block of the column kernels
 
+__constant__ double c_lines[2 * LINE_TAB_SIZE];
+
+template <int L>
+SP6_DEV const double* line_tab(int kind) {
+  return c_lines + kind * LINE_TAB_SIZE + line_tab_offset(L);
+}
+
 // ---------------------------------------------------------------------------
 // phi lines
 
-template <int L>
+template <int L, bool ACCUM>
 __global__ __launch_bounds__(CB) void k_phi(KDims d, KTab t, const double* __restrict__ Y,
-                                            double* __restrict__ T, int accum, double coef_sign,
-                                            int mask_in, double in_scale) {
+                                            double* __restrict__ T, double coef_sign, int mask_in,
+                                            double in_scale) {
   const int64_t gid = int64_t(blockIdx.x) * CB + threadIdx.x;
   const int64_t nouter = int64_t(d.n_eps) * d.n_r * d.n_th;
   if (gid >= nouter * d.plane) return;
@@ -46,16 +53,19 @@ __global__ __launch_bounds__(CB) void k_phi(KDims d, KTab t, const double* __res
   double v[L];
 #pragma unroll
   for (int k = 0; k < L; ++k) v[k] = Y[base + k * stride] * s_in;
-  double tv[L];
-  if (accum) {
+  double tv[ACCUM ? L : 1];
+  if constexpr (ACCUM) {
 #pragma unroll
     for (int k = 0; k < L; ++k) tv[k] = T[base + k * stride];
   }
   const double s = coef_sign * t.sin_Th[iTh] * t.sin_Ph[m] * t.inv_r[j] * t.inv_sin_th[l];
   eo_split<L>(v);
-  eo_pairs<L, L / 2, true>(t.eo_ph, 0, v, [&](int k, double z) {
+  eo_pairs<L, L / 2, true>(line_tab<L>(LT_DERIV), 0, v, [&](int k, double z) {
     const double val = s * z;
-    T[base + k * stride] = accum ? tv[k] + val : val;
+    if constexpr (ACCUM)
+      T[base + k * stride] = tv[k] + val;
+    else
+      T[base + k * stride] = val;
   });
 }
 
@@ -63,10 +73,10 @@ __global__ __launch_bounds__(CB) void k_phi(KDims d, KTab t, const double* __res
 // theta DFS lines: thread = (eps, r, k < n_phi/2, column c); it owns the orbit
 // {(k, c), (k + n_phi/2, c')} with c' the column at Phi_m + pi.
 
-template <int NTH>
+template <int NTH, bool ACCUM>
 __global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const double* __restrict__ Y,
-                                              double* __restrict__ T, int accum, double coef_sign,
-                                              int mask_in, double in_scale) {
+                                              double* __restrict__ T, double coef_sign, int mask_in,
+                                              double in_scale) {
   constexpr int L = 2 * NTH;
   const int hph = d.n_ph / 2;
   const int64_t gid = int64_t(blockIdx.x) * CB + threadIdx.x;
@@ -94,8 +104,8 @@ __global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const double* __r
     v[l] = Y[ba + l * rowstride] * s_in;
     v[L - 1 - l] = Y[bb + l * rowstride] * s_in;
   }
-  double tv[L];
-  if (accum) {
+  double tv[ACCUM ? L : 1];
+  if constexpr (ACCUM) {
 #pragma unroll
     for (int l = 0; l < NTH; ++l) {
       tv[l] = T[ba + l * rowstride];
@@ -106,10 +116,13 @@ __global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const double* __r
   // derivative is -z[L-1-l]; both signs cancel.
   const double s = coef_sign * t.sin_Th[iTh] * t.cos_Ph[m] * t.inv_r[j];
   eo_split<L>(v);
-  eo_pairs<L, NTH, true>(t.eo_th, 0, v, [&](int q, double z) {
+  eo_pairs<L, NTH, true>(line_tab<L>(LT_DERIV), 0, v, [&](int q, double z) {
     const double val = s * z;
     const int64_t a = (q < NTH) ? ba + q * rowstride : bb + (L - 1 - q) * rowstride;
-    T[a] = accum ? tv[q] + val : val;
+    if constexpr (ACCUM)
+      T[a] = tv[q] + val;
+    else
+      T[a] = val;
   });
 }
 
@@ -122,11 +135,12 @@ __global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const double* __r
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int KS>
+template <int KS, bool ACCUM>
 __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __restrict__ Y,
-                                               double* __restrict__ T, int accum, int transpose,
-                                               int mask_in, double in_scale) {
+                                               double* __restrict__ T, int transpose, int mask_in,
+                                               double in_scale) {
   constexpr int NRT = (KS + 3) / 4;
+  constexpr int NWV = CB / 64;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
@@ -137,24 +151,42 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
 #pragma unroll
     for (int s = 0; s < KS; ++s) a[rt][s] = Dp[(16 * rt + lr) * t.KP + 4 * s + lk];
 
-  const int64_t gpe = d.M / 16;  // column groups per energy group
-  const int64_t ngroups = gpe * d.n_eps;
-  const int nw = CB / 64;
-  for (int64_t g = int64_t(blockIdx.x) * nw + wave; g < ngroups; g += int64_t(gridDim.x) * nw) {
-    const int64_t e = g / gpe;
-    const int64_t col = (g % gpe) * 16 + lr;
-    const int64_t ebase = e * d.n_r * d.M + col;
-    const int iTh = int((col / d.n_Ph) % d.n_Th);
+  // column groups of 16; each workgroup walks one contiguous range of them, its
+  // wavefronts side by side (all sizes fit in 32 bits)
+  const int gpe = int(d.M / 16);
+  const int ngroups = gpe * d.n_eps;
+  const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
+  const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
+  const int64_t M = d.M;
+  for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
+    const int e = g / gpe;
+    const int col = (g - e * gpe) * 16 + lr;
+    const int64_t eb = int64_t(e) * d.n_r * M + col;
+    const int iTh = (col / d.n_Ph) % d.n_Th;
     double b[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const int row = 4 * s + lk;
-      double val = 0.0;
-      if (row < d.n_r) {
-        val = Y[ebase + row * d.M] * in_scale;
-        if (mask_in && is_inflow(d, t, row, iTh)) val = 0.0;
-      }
-      b[s] = val;
+      b[s] = row < d.n_r ? Y[eb + row * M] : 0.0;
+    }
+    double tv[ACCUM ? NRT * 4 : 1];
+    if constexpr (ACCUM) {
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * rt + lk + 4 * v;
+          tv[rt * 4 + v] = row < d.n_r ? T[eb + row * M] : 0.0;
+        }
+    }
+    if (mask_in) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        if (is_inflow(d, t, 4 * s + lk, iTh)) b[s] = 0.0;
+    }
+    if (in_scale != 1.0) {
+#pragma unroll
+      for (int s = 0; s < KS; ++s) b[s] *= in_scale;
     }
     v4d acc[NRT];
 #pragma unroll
@@ -170,9 +202,11 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
       for (int v = 0; v < 4; ++v) {
         const int row = 16 * rt + lk + 4 * v;
         if (row < d.n_r) {
-          const int64_t ad = ebase + row * d.M;
           const double val = cT * acc[rt][v];
-          T[ad] = accum ? T[ad] + val : val;
+          if constexpr (ACCUM)
+            T[eb + row * M] = tv[rt * 4 + v] + val;
+          else
+            T[eb + row * M] = val;
         }
       }
   }
@@ -194,7 +228,7 @@ __global__ __launch_bounds__(CB) void k_filter_phi(KDims d, KTab t, double* __re
 #pragma unroll
   for (int k = 0; k < L; ++k) v[k] = F[base + k * stride];
   eo_split<L>(v);
-  eo_pairs<L, L / 2, false>(t.fl_ph, 0, v, [&](int k, double z) { F[base + k * stride] = z; });
+  eo_pairs<L, L / 2, false>(line_tab<L>(LT_FILTER), 0, v, [&](int k, double z) { F[base + k * stride] = z; });
 }
 
 template <int NTH>
@@ -221,7 +255,7 @@ __global__ __launch_bounds__(CB) void k_filter_theta(KDims d, KTab t, double* __
     v[L - 1 - l] = F[bb + l * rowstride];
   }
   eo_split<L>(v);
-  eo_pairs<L, NTH, false>(t.fl_th, 0, v, [&](int q, double z) {
+  eo_pairs<L, NTH, false>(line_tab<L>(LT_FILTER), 0, v, [&](int q, double z) {
     const int64_t a = (q < NTH) ? ba + q * rowstride : bb + (L - 1 - q) * rowstride;
     F[a] = z;
   });
@@ -235,8 +269,13 @@ hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T,
                       double coef_sign, bool mask_in, double in_scale, hipStream_t s) {
   const unsigned g = grid_for(int64_t(d.n_eps) * d.n_r * d.n_th * d.plane);
   switch (d.n_ph) {
-#define CASE(N) \
-  case N: k_phi<N><<<g, CB, 0, s>>>(d, t, Y, T, accum, coef_sign, mask_in, in_scale); break;
+#define CASE(N)                                                                       \
+  case N:                                                                             \
+    if (accum)                                                                        \
+      k_phi<N, true><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);      \
+    else                                                                              \
+      k_phi<N, false><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);     \
+    break;
     CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -248,8 +287,13 @@ hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* 
                         double coef_sign, bool mask_in, double in_scale, hipStream_t s) {
   const unsigned g = grid_for(int64_t(d.n_eps) * d.n_r * (d.n_ph / 2) * d.plane);
   switch (d.n_th) {
-#define CASE(N) \
-  case N: k_theta<N><<<g, CB, 0, s>>>(d, t, Y, T, accum, coef_sign, mask_in, in_scale); break;
+#define CASE(N)                                                                       \
+  case N:                                                                             \
+    if (accum)                                                                        \
+      k_theta<N, true><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);    \
+    else                                                                              \
+      k_theta<N, false><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);   \
+    break;
     CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -257,16 +301,28 @@ hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* 
   return hipGetLastError();
 }
 
+template <int KS, bool ACCUM>
+void launch_radial_t(const KDims& d, const KTab& t, const double* Y, double* T, bool transpose, bool mask_in,
+                     double in_scale, hipStream_t s) {
+  const int64_t ngroups = (d.M / 16) * d.n_eps;
+  // a few resident waves of workgroups per compute unit
+  int64_t blocks = (ngroups + 3) / 4;
+  const int64_t cap = int64_t(d.ncu) * 8;
+  if (blocks > cap) blocks = cap;
+  k_radial<KS, ACCUM><<<unsigned(blocks), CB, 0, s>>>(d, t, Y, T, transpose, mask_in, in_scale);
+}
+
 hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
                          bool transpose, bool mask_in, double in_scale, hipStream_t s) {
-  const int64_t ngroups = (d.M / 16) * d.n_eps;
-  int64_t blocks = (ngroups + 3) / 4;
-  if (blocks > 4096) blocks = 4096;
-  const unsigned g = unsigned(blocks);
   const int KS = t.KP / 4;
   switch (KS) {
-#define CASE(N) \
-  case N: k_radial<N><<<g, CB, 0, s>>>(d, t, Y, T, accum, transpose, mask_in, in_scale); break;
+#define CASE(N)                                                                  \
+  case N:                                                                        \
+    if (accum)                                                                   \
+      launch_radial_t<N, true>(d, t, Y, T, transpose, mask_in, in_scale, s);     \
+    else                                                                         \
+      launch_radial_t<N, false>(d, t, Y, T, transpose, mask_in, in_scale, s);    \
+    break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
     CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16) CASE(17) CASE(18) CASE(19) CASE(20)
 #undef CASE
@@ -295,4 +351,8 @@ hipError_t launch_filter_columns(const KDims& d, const KTab& t, double* F, hipSt
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t init_line_tables_columns(const double* tab) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
 }

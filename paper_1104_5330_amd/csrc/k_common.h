@@ -45,6 +45,17 @@ SP6_DEV void eo_pairs(const TT* __restrict__ tab, int i0, const T (&v)[L], Emit&
 
 SP6_DEV int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Line-operator tables in constant memory.  The Fourier derivative and the
+// filter on an L-point periodic line depend on L only, so one copy per L serves
+// every handle.  Kind 0: derivative, kind 1: filter; each in even/odd form
+// (A then B, h x h, h = L/2), line lengths 4, 8, 16, 32, 64 back to back.
+// Uniform indices let the compiler read them with scalar loads.
+constexpr int line_tab_offset(int L) {
+  return L == 4 ? 0 : L == 8 ? 8 : L == 16 ? 40 : L == 32 ? 168 : L == 64 ? 680 : -1;
+}
+constexpr int LINE_TAB_SIZE = 2728;  // sum of 2 (L/2)^2 over L = 4 .. 64
+enum { LT_DERIV = 0, LT_FILTER = 1 };
+
 // inflow node test (Sect. 4.2): r_in with cos(Theta) > 0, r_out with cos(Theta) < 0
 SP6_DEV bool is_inflow(const KDims& d, const KTab& t, int j, int iTh) {
   if (!d.bc) return false;

@@ -14,6 +14,13 @@
 
 namespace {
 
+__constant__ double c_lines[2 * LINE_TAB_SIZE];
+
+template <int L>
+SP6_DEV const double* line_tab(int kind) {
+  return c_lines + kind * LINE_TAB_SIZE + line_tab_offset(L);
+}
+
 template <int NT>
 struct PC {
   static constexpr int L = 2 * NT;        // line length (Theta DFS line, Phi row)
@@ -93,97 +100,144 @@ SP6_DEV double line_coef(bool isTh, int q, int li, double inv_r, double cot_th, 
 }
 
 // ---------------------------------------------------------------------------
-// forward: L F (partial), right-hand side, or one RK4 stage
+// forward: L F (partial), right-hand side, or one RK4 stage.
+// Persistent workgroups walk over groups of NPW planes; while the lines and the
+// epilogue of one group are computed, the global loads of the next group are in
+// flight (register double buffering).
 
-template <int NT>
-__global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a) {
+struct PlaneInfo {
+  double inv_r, cot_th, kappa, sigma, eta, mean;
+  int j, pad;
+};
+
+template <int NT, bool NA, bool NY>
+__global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
   __shared__ double sY[C::PTSP];
   __shared__ double sR[2][C::PTSP];
-  __shared__ double sMean[C::NPW * NT];
-  __shared__ double sTh[NT], sPh[C::NF];
+  __shared__ double sTh[NT], sPh[C::NF], sCT[NT], sWm[NT];
+  __shared__ PlaneInfo sPl[C::NPW];
 
   const int tid = threadIdx.x;
-  const int64_t plane0 = int64_t(blockIdx.x) * C::NPW;
-  const int64_t gbase = plane0 * C::PLANE;
-  const int64_t npl = d.nplanes;
-  if (tid < NT) sTh[tid] = t.sin_Th[tid];
+  const int npl = int(d.nplanes);
+  if (tid < NT) {
+    sTh[tid] = t.sin_Th[tid];
+    sCT[tid] = t.cos_Th[tid];
+    sWm[tid] = t.wmean[tid];
+  }
   if (tid < C::NF) sPh[tid] = t.sin_Ph[tid];
-
-  double tv[C::PPT], av[C::PPT], yv[C::PPT];
-#pragma unroll
-  for (int q = 0; q < C::PPT; ++q) {
-    const int p = tid + q * C::NTHR;
-    const bool ok = plane0 + p / C::PLANE < npl;
-    const int64_t gp = gbase + p;
-    sY[C::lds(p)] = ok ? a.Yin[gp] : 0.0;
-    tv[q] = (ok && a.T) ? a.T[gp] : 0.0;
-    av[q] = (ok && a.accsrc) ? a.accsrc[gp] : 0.0;
-    yv[q] = (ok && a.ysrc) ? a.ysrc[gp] : 0.0;
-  }
-  __syncthreads();
-
-  {  // line phase
-    const int lane = tid & 63;
-    const int part = wave_uniform(tid >> 6);
-    const int pl = lane / C::LPP, li = lane % C::LPP;
-    const bool isTh = li < NT;
-    const LineMap<NT> lm = line_map<NT>(pl, li);
-    const int64_t pid = plane0 + pl;
-    const PlaneIdx pi = plane_index(d, pid < npl ? pid : 0);
-    const double inv_r = t.inv_r[pi.j], cot_th = t.cot_th[pi.l];
-    double v[C::L];
-#pragma unroll
-    for (int q = 0; q < C::L; ++q) v[q] = sY[lm.idx(q)];
-    if (part == 0 && !isTh) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < C::L; ++q) s += v[q];
-      sMean[pl * NT + (li - NT)] = t.wmean[li - NT] * s;
-    }
-    double* out = sR[isTh ? 0 : 1];
-    eo_split<C::L>(v);
-    eo_pairs<C::L, C::PPW, true>(t.eo_pl, part * C::PPW, v, [&](int q, double z) {
-      out[lm.idx(q)] = line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh) * z;
-    });
-  }
-  __syncthreads();
-
   const bool useTh = a.terms & 8u, usePh = a.terms & 16u;
+  const bool needT = a.T != nullptr;
+
+  double yin[C::PPT], tv[C::PPT], av[NA ? C::PPT : 1], yv[NY ? C::PPT : 1];
+  // each workgroup walks one contiguous range of plane groups
+  const int per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
+  const int gbeg = per_blk * blockIdx.x, gend = min(ngroups, gbeg + per_blk);
+  auto load = [&](int g, double* yi, double* ti, double* ai, double* yo) {
+    const int plane0 = g * C::NPW;
 #pragma unroll
-  for (int q = 0; q < C::PPT; ++q) {
-    const int p = tid + q * C::NTHR;
-    const int pl = p / C::PLANE;
-    const int64_t pid = plane0 + pl;
-    if (pid >= npl) continue;
-    const int64_t gp = gbase + p;
-    const int lp = C::lds(p);
-    double LY = tv[q];
-    if (useTh) LY += sR[0][lp];
-    if (usePh) LY += sR[1][lp];
-    if (a.mode == PM_APPLY) {
-      a.out[gp] = LY;
-      continue;
+    for (int q = 0; q < C::PPT; ++q) {
+      const int p = tid + q * C::NTHR;
+      const bool ok = g < gend && plane0 + p / C::PLANE < npl;
+      const int64_t gp = int64_t(plane0) * C::PLANE + p;
+      yi[q] = ok ? a.Yin[gp] : 0.0;
+      ti[q] = (ok && needT) ? a.T[gp] : 0.0;
+      if constexpr (NA) ai[q] = ok ? a.accsrc[gp] : 0.0;
+      if constexpr (NY) yo[q] = ok ? a.ysrc[gp] : 0.0;
     }
-    const int iTh = (p % C::PLANE) / C::NF;
-    const PlaneIdx pi = plane_index(d, pid);
-    const double Yv = sY[lp];
-    const double ka = cf.kappa[pid], et = cf.eta[pid];
-    double k = -LY + et - ka * Yv;
-    if (d.scattering) {
-      const double si = cf.sigma[pid];
-      double mean = 0.0;
+  };
+  int grp = gbeg;
+  load(grp, yin, tv, av, yv);
+  for (; grp < gend; ++grp) {
+    const int plane0 = grp * C::NPW;
 #pragma unroll
-      for (int ii = 0; ii < NT; ++ii) mean += sMean[pl * NT + ii];
-      k += si * (mean - Yv);
+    for (int q = 0; q < C::PPT; ++q) sY[C::lds(tid + q * C::NTHR)] = yin[q];
+    if (tid < C::NPW) {
+      const int pid = min(plane0 + tid, npl - 1);
+      const int l = (pid / d.n_ph) % d.n_th;
+      const int j = (pid / (d.n_ph * d.n_th)) % d.n_r;
+      PlaneInfo pi;
+      pi.inv_r = t.inv_r[j];
+      pi.cot_th = t.cot_th[l];
+      pi.kappa = a.mode == PM_APPLY ? 0.0 : cf.kappa[pid];
+      pi.eta = a.mode == PM_APPLY ? 0.0 : cf.eta[pid];
+      pi.sigma = (a.mode == PM_APPLY || !d.scattering) ? 0.0 : cf.sigma[pid];
+      pi.mean = 0.0;
+      pi.j = j;
+      pi.pad = 0;
+      sPl[tid] = pi;
     }
-    if (is_inflow(d, t, pi.j, iTh)) k = 0.0;
-    if (a.mode == PM_RHS) {
-      a.out[gp] = k;
-      continue;
+    __syncthreads();
+    double nyin[C::PPT], ntv[C::PPT], nav[NA ? C::PPT : 1], nyv[NY ? C::PPT : 1];
+    load(grp + 1, nyin, ntv, nav, nyv);
+
+    {  // line phase
+      const int lane = tid & 63;
+      const int part = wave_uniform(tid >> 6);
+      const int pl = lane / C::LPP, li = lane % C::LPP;
+      const bool isTh = li < NT;
+      const LineMap<NT> lm = line_map<NT>(pl, li);
+      const double inv_r = sPl[pl].inv_r, cot_th = sPl[pl].cot_th;
+      double v[C::L];
+#pragma unroll
+      for (int q = 0; q < C::L; ++q) v[q] = sY[lm.idx(q)];
+      if (d.scattering && a.mode != PM_APPLY && part == 0) {
+        // weighted row sum of each Phi row, reduced over the NT Phi lanes of the plane
+        double s = 0.0;
+        if (!isTh) {
+#pragma unroll
+          for (int q = 0; q < C::L; ++q) s += v[q];
+          s *= sWm[li - NT];
+        }
+#pragma unroll
+        for (int off = 1; off < NT; off <<= 1) s += __shfl_xor(s, off, 64);
+        if (li == NT) sPl[pl].mean = s;
+      }
+      double* out = sR[isTh ? 0 : 1];
+      eo_split<C::L>(v);
+      eo_pairs<C::L, C::PPW, true>(line_tab<C::L>(LT_DERIV), part * C::PPW, v, [&](int q, double z) {
+        out[lm.idx(q)] = line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh) * z;
+      });
     }
-    if (a.accdst) a.accdst[gp] = (a.accsrc ? av[q] : Yv) + a.cb * k;
-    if (a.ynext) a.ynext[gp] = (a.ysrc ? yv[q] : Yv) + a.cn * k;
+    __syncthreads();
+
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int p = tid + q * C::NTHR;
+      const int pl = p / C::PLANE;
+      if (plane0 + pl >= npl) continue;
+      const int64_t gp = int64_t(plane0) * C::PLANE + p;
+      const int lp = C::lds(p);
+      double LY = tv[q];
+      if (useTh) LY += sR[0][lp];
+      if (usePh) LY += sR[1][lp];
+      if (a.mode == PM_APPLY) {
+        a.out[gp] = LY;
+        continue;
+      }
+      const int iTh = (p % C::PLANE) / C::NF;
+      const PlaneInfo& pi = sPl[pl];
+      const double Yv = sY[lp];
+      double k = -LY + pi.eta - (pi.kappa + pi.sigma) * Yv + pi.sigma * pi.mean;
+      if (d.bc && ((pi.j == 0 && sCT[iTh] > 0.0) || (pi.j == d.n_r - 1 && sCT[iTh] < 0.0))) k = 0.0;
+      if (a.mode == PM_RHS) {
+        a.out[gp] = k;
+        continue;
+      }
+      double ab = Yv, yb = Yv;
+      if constexpr (NA) ab = av[q];
+      if constexpr (NY) yb = yv[q];
+      if (a.accdst) a.accdst[gp] = ab + a.cb * k;
+      if (a.ynext) a.ynext[gp] = yb + a.cn * k;
+    }
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      yin[q] = nyin[q];
+      tv[q] = ntv[q];
+      if constexpr (NA) av[q] = nav[q];
+      if constexpr (NY) yv[q] = nyv[q];
+    }
+    __syncthreads();
   }
 }
 
@@ -265,7 +319,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
     }
     double* out = sR[isTh ? 0 : 1];
     eo_split<C::L>(v);
-    eo_pairs<C::L, C::PPW, true>(t.eo_pl, part * C::PPW, v, [&](int q, double z) { out[lm.idx(q)] = -z; });
+    eo_pairs<C::L, C::PPW, true>(line_tab<C::L>(LT_DERIV), part * C::PPW, v, [&](int q, double z) { out[lm.idx(q)] = -z; });
   }
   __syncthreads();
 
@@ -342,7 +396,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_filter_plane(KDims d, KTab t, 
 #pragma unroll
     for (int q = 0; q < C::L; ++q) v[q] = sY[lm.idx(q)];
     eo_split<C::L>(v);
-    eo_pairs<C::L, C::PPW, false>(t.fl_pl, part * C::PPW, v, [&](int q, double z) { sR[lm.idx(q)] = z; });
+    eo_pairs<C::L, C::PPW, false>(line_tab<C::L>(LT_FILTER), part * C::PPW, v, [&](int q, double z) { sR[lm.idx(q)] = z; });
   }
   __syncthreads();
   if (!isTh) {
@@ -350,7 +404,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_filter_plane(KDims d, KTab t, 
 #pragma unroll
     for (int q = 0; q < C::L; ++q) v[q] = sR[lm.idx(q)];
     eo_split<C::L>(v);
-    eo_pairs<C::L, C::PPW, false>(t.fl_pl, part * C::PPW, v, [&](int q, double z) { sY[lm.idx(q)] = z; });
+    eo_pairs<C::L, C::PPW, false>(line_tab<C::L>(LT_FILTER), part * C::PPW, v, [&](int q, double z) { sY[lm.idx(q)] = z; });
   }
   __syncthreads();
 #pragma unroll
@@ -367,10 +421,37 @@ unsigned plane_blocks(const KDims& d) {
 
 }  // namespace
 
+// persistent grid: as many workgroups as can be resident at once
+template <typename K>
+unsigned persistent_blocks(const KDims& d, K kernel, int threads, int64_t work) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  const int64_t cap = int64_t(d.ncu) * per_cu;
+  return unsigned(work < cap ? work : cap);
+}
+
+template <int NT, bool NA, bool NY>
+void launch_plane_t(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
+  const int ng = int((d.nplanes + PC<NT>::NPW - 1) / PC<NT>::NPW);
+  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, NY>, PC<NT>::NTHR, ng);
+  k_plane<NT, NA, NY><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
+}
+
+template <int NT>
+void launch_plane_n(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
+  const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
+  if (na && ny) launch_plane_t<NT, true, true>(d, t, c, a, s);
+  else if (na) launch_plane_t<NT, true, false>(d, t, c, a, s);
+  else if (ny) launch_plane_t<NT, false, true>(d, t, c, a, s);
+  else launch_plane_t<NT, false, false>(d, t, c, a, s);
+}
+
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   switch (d.n_Th) {
-#define CASE(N) \
-  case N: k_plane<N><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a); break;
+#define CASE(N)                          \
+  case N:                                \
+    launch_plane_n<N>(d, t, c, a, s);    \
+    break;
     CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -415,4 +496,8 @@ hipError_t launch_filter_plane(const KDims& d, const KTab& t, double* F, hipStre
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t init_line_tables_plane(const double* tab) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
 }

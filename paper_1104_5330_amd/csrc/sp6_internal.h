@@ -19,6 +19,7 @@ struct KDims {
   int64_t P;        // all points
   int64_t nplanes;  // n_eps * n_r * n_th * n_ph
   int bc, scattering;
+  int ncu;          // compute units of the device (persistent grids)
 };
 
 struct KTab {
@@ -31,20 +32,11 @@ struct KTab {
   const double* cos_Ph;      // [n_Ph]
   const double* wmean;       // [n_Th]  w_i (2 pi / n_Ph) / (4 pi)
   const double* wflux;       // [n_Th]  w_i (2 pi / n_Ph) cos(Theta_i) where cos > 0, else 0
-  const double* eo_th;       // even/odd split of the 2 n_th DFS derivative (2 h^2, h = n_th)
-  const double* eo_ph;       // phi line derivative, h = n_ph / 2
-  const double* eo_pl;       // Theta DFS and Phi line derivative, h = n_Th (n_Ph = 2 n_Th)
-  const double* fl_th;       // filter, same layouts
-  const double* fl_ph;
-  const double* fl_pl;
   const double* Dpad;        // radial matrix, zero padded [NRP][KP]
   const double* DpadT;       // its transpose, same padding
   const double* qN;          // [n_r * n_th * n_Th] weights of the particle number
   const double* qJ;          // [n_th * n_Th] weights of the boundary flux (without r^2)
   // mixed precision copies
-  const float* eo_th_f;
-  const float* eo_ph_f;
-  const float* eo_pl_f;
   const float* Dsplit;       // bf16x3 split of Dpad as 3 float planes [3][NRP][KP]
   int KP, NRP;
 };
@@ -65,13 +57,17 @@ struct HostTables {
   std::vector<double> w_r, w_th, w_ph, w_Th, w_Ph;
   std::vector<double> Dr;  // n_r x n_r, row major
   std::vector<double> inv_r, inv_sin_th, cot_th, sin_Th, cos_Th, sin_Ph, cos_Ph, wmean, wflux;
-  std::vector<double> eo_th, eo_ph, eo_pl, fl_th, fl_ph, fl_pl;
   std::vector<double> Dpad, DpadT;
   std::vector<double> qN, qJ;
   int KP = 0, NRP = 0;
 };
 
 void build_host_tables(const sp6_desc& d, HostTables& t);
+// [2][2728]: derivative then filter tables of every supported line length
+std::vector<double> build_line_tables();
+// copy the line tables into the constant memory of each kernel file (current device)
+hipError_t init_line_tables_columns(const double* tab);
+hipError_t init_line_tables_plane(const double* tab);
 std::string validate_desc(const sp6_desc& d, sp6_status* code);
 
 // ---------------------------------------------------------------------------

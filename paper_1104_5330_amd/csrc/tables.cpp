@@ -82,6 +82,16 @@ std::vector<double> clenshaw_curtis(int n_r) {
 
 }  // namespace
 
+std::vector<double> build_line_tables() {
+  std::vector<double> out;
+  for (int kind = 0; kind < 2; ++kind)
+    for (int L = 4; L <= 64; L *= 2) {
+      std::vector<double> ab = even_odd(kind == 0 ? fourier_matrix(L) : filter_matrix(L), L);
+      out.insert(out.end(), ab.begin(), ab.end());
+    }
+  return out;
+}
+
 std::string validate_desc(const sp6_desc& d, sp6_status* code) {
   char buf[256];
   *code = SP6_ERR_SHAPE;
@@ -169,14 +179,6 @@ void build_host_tables(const sp6_desc& d, HostTables& t) {
       t.Dpad[size_t(i) * t.KP + j] = D[size_t(i) * nr + j];
       t.DpadT[size_t(i) * t.KP + j] = D[size_t(j) * nr + i];
     }
-
-  // angular derivative and filter tables
-  t.eo_th = even_odd(fourier_matrix(2 * nth), 2 * nth);
-  t.eo_ph = even_odd(fourier_matrix(nph), nph);
-  t.eo_pl = even_odd(fourier_matrix(2 * nTh), 2 * nTh);
-  t.fl_th = even_odd(filter_matrix(2 * nth), 2 * nth);
-  t.fl_ph = even_odd(filter_matrix(nph), nph);
-  t.fl_pl = even_odd(filter_matrix(2 * nTh), 2 * nTh);
 
   // pointwise coefficient factors
   t.inv_r.resize(nr);
