@@ -192,15 +192,55 @@ hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transp
   return e;
 }
 
+// mixed path: the r, theta and phi terms of L Y in FP32 (Y stored in FP64 or FP32)
+hipError_t column_terms_mixed(sp6_grid g, const void* Y, bool y_f32, uint32_t terms, bool* wrote,
+                              Timer* tm = nullptr) {
+  hipError_t e = hipSuccess;
+  bool acc = false;
+  if (terms & 4u) {
+    e = launch_phi_mixed(g->d, g->t, Y, y_f32, g->Tf, acc, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_PHI);
+    if (e != hipSuccess) return e;
+    acc = true;
+  }
+  if (terms & 2u) {
+    e = launch_theta_mixed(g->d, g->t, Y, y_f32, g->Tf, acc, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_THETA);
+    if (e != hipSuccess) return e;
+    acc = true;
+  }
+  if (terms & 1u) {
+    e = launch_radial_bf16x3(g->d, g->t, Y, y_f32, g->Tf, acc, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_RADIAL);
+    if (e != hipSuccess) return e;
+    acc = true;
+  }
+  *wrote = acc;
+  return e;
+}
+
+hipError_t ensure_f32(sp6_grid g, float** p) {
+  if (*p) return hipSuccess;
+  return g->alloc(reinterpret_cast<void**>(p), size_t(g->d.P) * sizeof(float));
+}
+
 sp6_status fp64_rhs_like(sp6_grid g, const double* F, double* out, int mode, uint32_t terms) {
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
-  HIP_TRY(ensure(g, &g->T, state_bytes(g)), "allocate scratch");
+  const bool mixed = g->desc.precision == SP6_MIXED;
   bool wrote = false;
-  HIP_TRY(column_terms(g, F, terms, false, false, 1.0, &wrote), "column passes");
+  if (mixed) {
+    HIP_TRY(ensure_f32(g, &g->Tf), "allocate scratch");
+    HIP_TRY(column_terms_mixed(g, F, false, terms, &wrote), "column passes");
+  } else {
+    HIP_TRY(ensure(g, &g->T, state_bytes(g)), "allocate scratch");
+    HIP_TRY(column_terms(g, F, terms, false, false, 1.0, &wrote), "column passes");
+  }
   StageArgs a{};
   a.mode = mode;
   a.Yin = F;
-  a.T = wrote ? g->T : nullptr;
+  a.mixed = mixed;
+  a.yin_f32 = 0;
+  a.T = wrote ? (mixed ? static_cast<const void*>(g->Tf) : static_cast<const void*>(g->T)) : nullptr;
   a.out = out;
   a.terms = terms;
   HIP_TRY(launch_plane(g->d, g->t, g->c, a, g->stream), "plane pass");
@@ -299,6 +339,11 @@ sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
 #undef UP
   t.KP = h.KP;
   t.NRP = h.NRP;
+  if (desc->precision == SP6_MIXED) {
+    std::vector<uint16_t> split;
+    build_radial_split(h, desc->n_r, split, &t.KP3);
+    if ((e = upload(g, split, &t.Dsplit)) != hipSuccess) goto fail_hip;
+  }
   {
     const size_t cb = size_t(d.nplanes) * sizeof(double);
     const size_t gb = size_t(d.n_eps) * d.M * sizeof(double);
@@ -458,31 +503,49 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
   if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
   if (nsteps == 0) return SP6_OK;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
-  HIP_TRY(ensure_step_scratch(g), "allocate scratch");
+  const bool mixed = g->desc.precision == SP6_MIXED;
+  if (mixed) {
+    HIP_TRY(ensure_f32(g, &g->Yf), "allocate scratch");
+    HIP_TRY(ensure_f32(g, &g->Tf), "allocate scratch");
+    HIP_TRY(ensure(g, &g->acc, state_bytes(g)), "allocate scratch");
+  } else {
+    HIP_TRY(ensure_step_scratch(g), "allocate scratch");
+  }
   const KDims& d = g->d;
   if (tm) HIP_TRY(tm->mark(g->stream, -1), "event");
   for (int32_t n = 0; n < nsteps; ++n) {
     for (int s = 1; s <= 4; ++s) {
-      const double* Yin = (s == 1) ? F : g->Ybuf;
       bool wrote = false;
-      HIP_TRY(column_terms(g, Yin, 7u, false, false, 1.0, &wrote, tm), "column passes");
       StageArgs a{};
       a.mode = PM_STAGE;
-      a.Yin = Yin;
-      a.T = g->T;
       a.terms = 31u;
+      a.mixed = mixed;
+      if (mixed) {
+        // stage 1 reads the FP64 state; later stages the FP32 stage copy
+        const void* Yin = (s == 1) ? static_cast<const void*>(F) : static_cast<const void*>(g->Yf);
+        HIP_TRY(column_terms_mixed(g, Yin, s != 1, 7u, &wrote, tm), "column passes");
+        a.Yin = Yin;
+        a.yin_f32 = s != 1;
+        a.T = g->Tf;
+      } else {
+        const double* Yin = (s == 1) ? F : g->Ybuf;
+        HIP_TRY(column_terms(g, Yin, 7u, false, false, 1.0, &wrote, tm), "column passes");
+        a.Yin = Yin;
+        a.T = g->T;
+      }
+      void* ybuf = mixed ? static_cast<void*>(g->Yf) : static_cast<void*>(g->Ybuf);
       switch (s) {
         case 1:
           a.accsrc = nullptr, a.accdst = g->acc, a.cb = dt / 6.0;
-          a.ysrc = nullptr, a.ynext = g->Ybuf, a.cn = 0.5 * dt;
+          a.ysrc = nullptr, a.ynext = ybuf, a.cn = 0.5 * dt;
           break;
         case 2:
           a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
-          a.ysrc = F, a.ynext = g->Ybuf, a.cn = 0.5 * dt;
+          a.ysrc = F, a.ynext = ybuf, a.cn = 0.5 * dt;
           break;
         case 3:
           a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
-          a.ysrc = F, a.ynext = g->Ybuf, a.cn = dt;
+          a.ysrc = F, a.ynext = ybuf, a.cn = dt;
           break;
         default:
           a.accsrc = g->acc, a.accdst = F, a.cb = dt / 6.0;

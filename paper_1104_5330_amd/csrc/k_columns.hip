@@ -24,18 +24,24 @@ namespace {
 constexpr int CB = 256;  // threads per block of the column kernels
 
 __constant__ double c_lines[2 * LINE_TAB_SIZE];
+__constant__ float c_lines_f[2 * LINE_TAB_SIZE];  // FP32 copy for the mixed path
 
-template <int L>
-SP6_DEV const double* line_tab(int kind) {
-  return c_lines + kind * LINE_TAB_SIZE + line_tab_offset(L);
+template <int L, typename TC = double>
+SP6_DEV const TC* line_tab(int kind) {
+  if constexpr (sizeof(TC) == 8)
+    return c_lines + kind * LINE_TAB_SIZE + line_tab_offset(L);
+  else
+    return c_lines_f + kind * LINE_TAB_SIZE + line_tab_offset(L);
 }
 
 // ---------------------------------------------------------------------------
 // phi lines
 
-template <int L, bool ACCUM>
-__global__ __launch_bounds__(CB) void k_phi(KDims d, KTab t, const double* __restrict__ Y,
-                                            double* __restrict__ T, double coef_sign, int mask_in,
+// TI: stored type of the input state, TO: stored type of T and compute type
+// (double, double) on the FP64 path; (double or float, float) on the mixed path.
+template <int L, bool ACCUM, typename TI, typename TO>
+__global__ __launch_bounds__(CB) void k_phi(KDims d, KTab t, const TI* __restrict__ Y,
+                                            TO* __restrict__ T, double coef_sign, int mask_in,
                                             double in_scale) {
   const int64_t gid = int64_t(blockIdx.x) * CB + threadIdx.x;
   const int64_t nouter = int64_t(d.n_eps) * d.n_r * d.n_th;
@@ -48,20 +54,20 @@ __global__ __launch_bounds__(CB) void k_phi(KDims d, KTab t, const double* __res
   const int64_t stride = d.plane;
   const int64_t base = o * (int64_t(L) * stride) + c;
 
-  double s_in = in_scale;
-  if (mask_in && is_inflow(d, t, j, iTh)) s_in = 0.0;
-  double v[L];
+  TO s_in = TO(in_scale);
+  if (mask_in && is_inflow(d, t, j, iTh)) s_in = TO(0);
+  TO v[L];
 #pragma unroll
-  for (int k = 0; k < L; ++k) v[k] = Y[base + k * stride] * s_in;
-  double tv[ACCUM ? L : 1];
+  for (int k = 0; k < L; ++k) v[k] = TO(Y[base + k * stride]) * s_in;
+  TO tv[ACCUM ? L : 1];
   if constexpr (ACCUM) {
 #pragma unroll
     for (int k = 0; k < L; ++k) tv[k] = T[base + k * stride];
   }
-  const double s = coef_sign * t.sin_Th[iTh] * t.sin_Ph[m] * t.inv_r[j] * t.inv_sin_th[l];
+  const TO s = TO(coef_sign * t.sin_Th[iTh] * t.sin_Ph[m] * t.inv_r[j] * t.inv_sin_th[l]);
   eo_split<L>(v);
-  eo_pairs<L, L / 2, true>(line_tab<L>(LT_DERIV), 0, v, [&](int k, double z) {
-    const double val = s * z;
+  eo_pairs<L, L / 2, true>(line_tab<L, TO>(LT_DERIV), 0, v, [&](int k, TO z) {
+    const TO val = s * z;
     if constexpr (ACCUM)
       T[base + k * stride] = tv[k] + val;
     else
@@ -73,9 +79,9 @@ __global__ __launch_bounds__(CB) void k_phi(KDims d, KTab t, const double* __res
 // theta DFS lines: thread = (eps, r, k < n_phi/2, column c); it owns the orbit
 // {(k, c), (k + n_phi/2, c')} with c' the column at Phi_m + pi.
 
-template <int NTH, bool ACCUM>
-__global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const double* __restrict__ Y,
-                                              double* __restrict__ T, double coef_sign, int mask_in,
+template <int NTH, bool ACCUM, typename TI, typename TO>
+__global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const TI* __restrict__ Y,
+                                              TO* __restrict__ T, double coef_sign, int mask_in,
                                               double in_scale) {
   constexpr int L = 2 * NTH;
   const int hph = d.n_ph / 2;
@@ -96,15 +102,15 @@ __global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const double* __r
   const int64_t ba = base + int64_t(k) * d.plane + c;
   const int64_t bb = base + int64_t(kp) * d.plane + cp;
 
-  double s_in = in_scale;
-  if (mask_in && is_inflow(d, t, j, iTh)) s_in = 0.0;
-  double v[L];
+  TO s_in = TO(in_scale);
+  if (mask_in && is_inflow(d, t, j, iTh)) s_in = TO(0);
+  TO v[L];
 #pragma unroll
   for (int l = 0; l < NTH; ++l) {
-    v[l] = Y[ba + l * rowstride] * s_in;
-    v[L - 1 - l] = Y[bb + l * rowstride] * s_in;
+    v[l] = TO(Y[ba + l * rowstride]) * s_in;
+    v[L - 1 - l] = TO(Y[bb + l * rowstride]) * s_in;
   }
-  double tv[ACCUM ? L : 1];
+  TO tv[ACCUM ? L : 1];
   if constexpr (ACCUM) {
 #pragma unroll
     for (int l = 0; l < NTH; ++l) {
@@ -114,10 +120,10 @@ __global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const double* __r
   }
   // partner coefficient is -s (cos(Phi + pi) = -cos Phi) and the partner
   // derivative is -z[L-1-l]; both signs cancel.
-  const double s = coef_sign * t.sin_Th[iTh] * t.cos_Ph[m] * t.inv_r[j];
+  const TO s = TO(coef_sign * t.sin_Th[iTh] * t.cos_Ph[m] * t.inv_r[j]);
   eo_split<L>(v);
-  eo_pairs<L, NTH, true>(line_tab<L>(LT_DERIV), 0, v, [&](int q, double z) {
-    const double val = s * z;
+  eo_pairs<L, NTH, true>(line_tab<L, TO>(LT_DERIV), 0, v, [&](int q, TO z) {
+    const TO val = s * z;
     const int64_t a = (q < NTH) ? ba + q * rowstride : bb + (L - 1 - q) * rowstride;
     if constexpr (ACCUM)
       T[a] = tv[q] + val;
@@ -263,19 +269,36 @@ __global__ __launch_bounds__(CB) void k_filter_theta(KDims d, KTab t, double* __
 
 unsigned grid_for(int64_t threads) { return unsigned((threads + CB - 1) / CB); }
 
-}  // namespace
-
-hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
-                      double coef_sign, bool mask_in, double in_scale, hipStream_t s) {
+template <int L, typename TI, typename TO>
+void launch_phi_t(const KDims& d, const KTab& t, const void* Y, void* T, bool accum, double coef_sign,
+                  bool mask_in, double in_scale, hipStream_t s) {
   const unsigned g = grid_for(int64_t(d.n_eps) * d.n_r * d.n_th * d.plane);
+  const TI* y = static_cast<const TI*>(Y);
+  TO* o = static_cast<TO*>(T);
+  if (accum)
+    k_phi<L, true, TI, TO><<<g, CB, 0, s>>>(d, t, y, o, coef_sign, mask_in, in_scale);
+  else
+    k_phi<L, false, TI, TO><<<g, CB, 0, s>>>(d, t, y, o, coef_sign, mask_in, in_scale);
+}
+
+template <int NTH, typename TI, typename TO>
+void launch_theta_t(const KDims& d, const KTab& t, const void* Y, void* T, bool accum, double coef_sign,
+                    bool mask_in, double in_scale, hipStream_t s) {
+  const unsigned g = grid_for(int64_t(d.n_eps) * d.n_r * (d.n_ph / 2) * d.plane);
+  const TI* y = static_cast<const TI*>(Y);
+  TO* o = static_cast<TO*>(T);
+  if (accum)
+    k_theta<NTH, true, TI, TO><<<g, CB, 0, s>>>(d, t, y, o, coef_sign, mask_in, in_scale);
+  else
+    k_theta<NTH, false, TI, TO><<<g, CB, 0, s>>>(d, t, y, o, coef_sign, mask_in, in_scale);
+}
+
+template <typename TI, typename TO>
+hipError_t launch_phi_p(const KDims& d, const KTab& t, const void* Y, void* T, bool accum, double coef_sign,
+                        bool mask_in, double in_scale, hipStream_t s) {
   switch (d.n_ph) {
-#define CASE(N)                                                                       \
-  case N:                                                                             \
-    if (accum)                                                                        \
-      k_phi<N, true><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);      \
-    else                                                                              \
-      k_phi<N, false><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);     \
-    break;
+#define CASE(N) \
+  case N: launch_phi_t<N, TI, TO>(d, t, Y, T, accum, coef_sign, mask_in, in_scale, s); break;
     CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -283,17 +306,12 @@ hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T,
   return hipGetLastError();
 }
 
-hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
-                        double coef_sign, bool mask_in, double in_scale, hipStream_t s) {
-  const unsigned g = grid_for(int64_t(d.n_eps) * d.n_r * (d.n_ph / 2) * d.plane);
+template <typename TI, typename TO>
+hipError_t launch_theta_p(const KDims& d, const KTab& t, const void* Y, void* T, bool accum, double coef_sign,
+                          bool mask_in, double in_scale, hipStream_t s) {
   switch (d.n_th) {
-#define CASE(N)                                                                       \
-  case N:                                                                             \
-    if (accum)                                                                        \
-      k_theta<N, true><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);    \
-    else                                                                              \
-      k_theta<N, false><<<g, CB, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale);   \
-    break;
+#define CASE(N) \
+  case N: launch_theta_t<N, TI, TO>(d, t, Y, T, accum, coef_sign, mask_in, in_scale, s); break;
     CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -310,6 +328,30 @@ void launch_radial_t(const KDims& d, const KTab& t, const double* Y, double* T, 
   const int64_t cap = int64_t(d.ncu) * 8;
   if (blocks > cap) blocks = cap;
   k_radial<KS, ACCUM><<<unsigned(blocks), CB, 0, s>>>(d, t, Y, T, transpose, mask_in, in_scale);
+}
+
+}  // namespace
+
+hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
+                      double coef_sign, bool mask_in, double in_scale, hipStream_t s) {
+  return launch_phi_p<double, double>(d, t, Y, T, accum, coef_sign, mask_in, in_scale, s);
+}
+
+hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
+                        double coef_sign, bool mask_in, double in_scale, hipStream_t s) {
+  return launch_theta_p<double, double>(d, t, Y, T, accum, coef_sign, mask_in, in_scale, s);
+}
+
+hipError_t launch_phi_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, bool accum,
+                            hipStream_t s) {
+  return y_f32 ? launch_phi_p<float, float>(d, t, Y, T, accum, 1.0, false, 1.0, s)
+               : launch_phi_p<double, float>(d, t, Y, T, accum, 1.0, false, 1.0, s);
+}
+
+hipError_t launch_theta_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, bool accum,
+                              hipStream_t s) {
+  return y_f32 ? launch_theta_p<float, float>(d, t, Y, T, accum, 1.0, false, 1.0, s)
+               : launch_theta_p<double, float>(d, t, Y, T, accum, 1.0, false, 1.0, s);
 }
 
 hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
@@ -354,5 +396,9 @@ hipError_t launch_filter_columns(const KDims& d, const KTab& t, double* F, hipSt
 }
 
 hipError_t init_line_tables_columns(const double* tab) {
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  float f[2 * LINE_TAB_SIZE];
+  for (int i = 0; i < 2 * LINE_TAB_SIZE; ++i) f[i] = float(tab[i]);
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_lines_f), f, sizeof f, 0, hipMemcpyHostToDevice);
 }

@@ -15,10 +15,14 @@
 namespace {
 
 __constant__ double c_lines[2 * LINE_TAB_SIZE];
+__constant__ float c_lines_f[2 * LINE_TAB_SIZE];  // FP32 copy for the mixed path
 
-template <int L>
-SP6_DEV const double* line_tab(int kind) {
-  return c_lines + kind * LINE_TAB_SIZE + line_tab_offset(L);
+template <int L, typename TC = double>
+SP6_DEV const TC* line_tab(int kind) {
+  if constexpr (sizeof(TC) == 8)
+    return c_lines + kind * LINE_TAB_SIZE + line_tab_offset(L);
+  else
+    return c_lines_f + kind * LINE_TAB_SIZE + line_tab_offset(L);
 }
 
 template <int NT>
@@ -110,11 +114,14 @@ struct PlaneInfo {
   int j, pad;
 };
 
-template <int NT, bool NA, bool NY>
+// TY: stored type of the stage input, TO: stored type of T and of the next stage
+// input, TC: type of the line derivatives.  The collision term, the inflow mask
+// and the RK update are FP64 in every instantiation.
+template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC>
 __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
-  __shared__ double sY[C::PTSP];
-  __shared__ double sR[2][C::PTSP];
+  __shared__ TY sY[C::PTSP];
+  __shared__ TC sR[2][C::PTSP];
   __shared__ double sTh[NT], sPh[C::NF], sCT[NT], sWm[NT];
   __shared__ PlaneInfo sPl[C::NPW];
 
@@ -128,20 +135,27 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
   if (tid < C::NF) sPh[tid] = t.sin_Ph[tid];
   const bool useTh = a.terms & 8u, usePh = a.terms & 16u;
   const bool needT = a.T != nullptr;
+  // ynext may be Yin itself (stages 2 and 3 update the stage buffer in place,
+  // each workgroup only rewriting the planes it has already read): no restrict
+  const TY* Yin = static_cast<const TY*>(a.Yin);
+  const TO* Tin = static_cast<const TO*>(a.T);
+  TO* ynext = static_cast<TO*>(a.ynext);
 
-  double yin[C::PPT], tv[C::PPT], av[NA ? C::PPT : 1], yv[NY ? C::PPT : 1];
+  TY yin[C::PPT];
+  TO tv[C::PPT];
+  double av[NA ? C::PPT : 1], yv[NY ? C::PPT : 1];
   // each workgroup walks one contiguous range of plane groups
   const int per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
   const int gbeg = per_blk * blockIdx.x, gend = min(ngroups, gbeg + per_blk);
-  auto load = [&](int g, double* yi, double* ti, double* ai, double* yo) {
+  auto load = [&](int g, TY* yi, TO* ti, double* ai, double* yo) {
     const int plane0 = g * C::NPW;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int p = tid + q * C::NTHR;
       const bool ok = g < gend && plane0 + p / C::PLANE < npl;
       const int64_t gp = int64_t(plane0) * C::PLANE + p;
-      yi[q] = ok ? a.Yin[gp] : 0.0;
-      ti[q] = (ok && needT) ? a.T[gp] : 0.0;
+      yi[q] = ok ? Yin[gp] : TY(0);
+      ti[q] = (ok && needT) ? Tin[gp] : TO(0);
       if constexpr (NA) ai[q] = ok ? a.accsrc[gp] : 0.0;
       if constexpr (NY) yo[q] = ok ? a.ysrc[gp] : 0.0;
     }
@@ -168,7 +182,9 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       sPl[tid] = pi;
     }
     __syncthreads();
-    double nyin[C::PPT], ntv[C::PPT], nav[NA ? C::PPT : 1], nyv[NY ? C::PPT : 1];
+    TY nyin[C::PPT];
+    TO ntv[C::PPT];
+    double nav[NA ? C::PPT : 1], nyv[NY ? C::PPT : 1];
     load(grp + 1, nyin, ntv, nav, nyv);
 
     {  // line phase
@@ -178,25 +194,25 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       const bool isTh = li < NT;
       const LineMap<NT> lm = line_map<NT>(pl, li);
       const double inv_r = sPl[pl].inv_r, cot_th = sPl[pl].cot_th;
-      double v[C::L];
+      TC v[C::L];
 #pragma unroll
-      for (int q = 0; q < C::L; ++q) v[q] = sY[lm.idx(q)];
+      for (int q = 0; q < C::L; ++q) v[q] = TC(sY[lm.idx(q)]);
       if (d.scattering && a.mode != PM_APPLY && part == 0) {
-        // weighted row sum of each Phi row, reduced over the NT Phi lanes of the plane
+        // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
         double s = 0.0;
         if (!isTh) {
 #pragma unroll
-          for (int q = 0; q < C::L; ++q) s += v[q];
+          for (int q = 0; q < C::L; ++q) s += double(sY[lm.idx(q)]);
           s *= sWm[li - NT];
         }
 #pragma unroll
         for (int off = 1; off < NT; off <<= 1) s += __shfl_xor(s, off, 64);
         if (li == NT) sPl[pl].mean = s;
       }
-      double* out = sR[isTh ? 0 : 1];
+      TC* out = sR[isTh ? 0 : 1];
       eo_split<C::L>(v);
-      eo_pairs<C::L, C::PPW, true>(line_tab<C::L>(LT_DERIV), part * C::PPW, v, [&](int q, double z) {
-        out[lm.idx(q)] = line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh) * z;
+      eo_pairs<C::L, C::PPW, true>(line_tab<C::L, TC>(LT_DERIV), part * C::PPW, v, [&](int q, TC z) {
+        out[lm.idx(q)] = TC(line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh)) * z;
       });
     }
     __syncthreads();
@@ -208,16 +224,16 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       if (plane0 + pl >= npl) continue;
       const int64_t gp = int64_t(plane0) * C::PLANE + p;
       const int lp = C::lds(p);
-      double LY = tv[q];
-      if (useTh) LY += sR[0][lp];
-      if (usePh) LY += sR[1][lp];
+      double LY = double(tv[q]);
+      if (useTh) LY += double(sR[0][lp]);
+      if (usePh) LY += double(sR[1][lp]);
       if (a.mode == PM_APPLY) {
         a.out[gp] = LY;
         continue;
       }
       const int iTh = (p % C::PLANE) / C::NF;
       const PlaneInfo& pi = sPl[pl];
-      const double Yv = sY[lp];
+      const double Yv = double(sY[lp]);
       double k = -LY + pi.eta - (pi.kappa + pi.sigma) * Yv + pi.sigma * pi.mean;
       if (d.bc && ((pi.j == 0 && sCT[iTh] > 0.0) || (pi.j == d.n_r - 1 && sCT[iTh] < 0.0))) k = 0.0;
       if (a.mode == PM_RHS) {
@@ -228,7 +244,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       if constexpr (NA) ab = av[q];
       if constexpr (NY) yb = yv[q];
       if (a.accdst) a.accdst[gp] = ab + a.cb * k;
-      if (a.ynext) a.ynext[gp] = yb + a.cn * k;
+      if (ynext) ynext[gp] = TO(yb + a.cn * k);
     }
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
@@ -430,20 +446,30 @@ unsigned persistent_blocks(const KDims& d, K kernel, int threads, int64_t work) 
   return unsigned(work < cap ? work : cap);
 }
 
-template <int NT, bool NA, bool NY>
+template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC>
 void launch_plane_t(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   const int ng = int((d.nplanes + PC<NT>::NPW - 1) / PC<NT>::NPW);
-  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, NY>, PC<NT>::NTHR, ng);
-  k_plane<NT, NA, NY><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
+  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, NY, TY, TO, TC>, PC<NT>::NTHR, ng);
+  k_plane<NT, NA, NY, TY, TO, TC><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
+}
+
+template <int NT, typename TY, typename TO, typename TC>
+void launch_plane_nt(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
+  const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
+  if (na && ny) launch_plane_t<NT, true, true, TY, TO, TC>(d, t, c, a, s);
+  else if (na) launch_plane_t<NT, true, false, TY, TO, TC>(d, t, c, a, s);
+  else if (ny) launch_plane_t<NT, false, true, TY, TO, TC>(d, t, c, a, s);
+  else launch_plane_t<NT, false, false, TY, TO, TC>(d, t, c, a, s);
 }
 
 template <int NT>
 void launch_plane_n(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
-  const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
-  if (na && ny) launch_plane_t<NT, true, true>(d, t, c, a, s);
-  else if (na) launch_plane_t<NT, true, false>(d, t, c, a, s);
-  else if (ny) launch_plane_t<NT, false, true>(d, t, c, a, s);
-  else launch_plane_t<NT, false, false>(d, t, c, a, s);
+  if (!a.mixed)
+    launch_plane_nt<NT, double, double, double>(d, t, c, a, s);
+  else if (a.yin_f32)
+    launch_plane_nt<NT, float, float, float>(d, t, c, a, s);
+  else
+    launch_plane_nt<NT, double, float, float>(d, t, c, a, s);
 }
 
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
@@ -499,5 +525,9 @@ hipError_t launch_filter_plane(const KDims& d, const KTab& t, double* F, hipStre
 }
 
 hipError_t init_line_tables_plane(const double* tab) {
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  float f[2 * LINE_TAB_SIZE];
+  for (int i = 0; i < 2 * LINE_TAB_SIZE; ++i) f[i] = float(tab[i]);
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_lines_f), f, sizeof f, 0, hipMemcpyHostToDevice);
 }

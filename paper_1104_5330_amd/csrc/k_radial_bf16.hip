@@ -1,0 +1,175 @@
+// Mixed-precision radial pass: cos(Theta) * (D_r Y) with D_r and Y each split
+// into three bf16 terms (D = D1 + D2 + D3, Y = Y1 + Y2 + Y3) and the six leading
+// cross products D1Y1, D1Y2, D2Y1, D1Y3, D2Y2, D3Y1 accumulated in FP32 on
+// v_mfma_f32_16x16x32_bf16 (the "bf16x3" scheme of Henry, Tang and Heinecke,
+// ARITH 2019).  Together they carry about 24 significant bits, the precision of
+// the FP32 stage copies they act on.
+//
+// Operand layouts of v_mfma_f32_16x16x32_bf16 (lane l, element e = 0..7):
+//   A (16 x 32): A[l % 16][8 (l / 16) + e];  B (32 x 16): B[8 (l / 16) + e][l % 16];
+//   C (16 x 16): register v holds C[4 (l / 16) + v][l % 16].
+#include <cstring>
+
+#include "k_common.h"
+
+namespace {
+
+constexpr int CB = 256;
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+SP6_DEV void split3(float x, __bf16& a, __bf16& b, __bf16& c) {
+  a = (__bf16)x;
+  const float r1 = x - float(a);
+  b = (__bf16)r1;
+  c = (__bf16)(r1 - float(b));
+}
+
+// NRT row tiles of 16, KS k-steps of 32 (n_r <= 32 KS, 16 NRT)
+template <int NRT, bool ACCUM, typename TI>
+__global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI* __restrict__ Y,
+                                                      float* __restrict__ T) {
+  constexpr int KS = (NRT + 1) / 2;
+  constexpr int NWV = CB / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  // A operands: three bf16 planes of the padded matrix, 8 consecutive k per lane
+  v8bf A[3][NRT][KS];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const uint16_t* src = t.Dsplit + (size_t(p) * t.NRP + 16 * rt + lr) * t.KP3 + 32 * s + 8 * lg;
+        const uint4 raw = *reinterpret_cast<const uint4*>(src);
+        __builtin_memcpy(&A[p][rt][s], &raw, 16);
+      }
+  const int gpe = int(d.M / 16);
+  const int ngroups = gpe * d.n_eps;
+  const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
+  const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
+  const int64_t M = d.M;
+  for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
+    const int e = g / gpe;
+    const int col = (g - e * gpe) * 16 + lr;
+    const int64_t eb = int64_t(e) * d.n_r * M + col;
+    v8bf B[3][KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int row = 32 * s + 8 * lg + q;
+        const float y = row < d.n_r ? float(Y[eb + row * M]) : 0.0f;
+        __bf16 b1, b2, b3;
+        split3(y, b1, b2, b3);
+        B[0][s][q] = b1;
+        B[1][s][q] = b2;
+        B[2][s][q] = b3;
+      }
+    float tv[ACCUM ? NRT * 4 : 1];
+    if constexpr (ACCUM) {
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * rt + 4 * lg + v;
+          tv[rt * 4 + v] = row < d.n_r ? T[eb + row * M] : 0.0f;
+        }
+    }
+    v4f acc[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) {
+      acc[rt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        // smallest products first
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[2][rt][s], B[0][s], acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1][rt][s], B[1][s], acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0][rt][s], B[2][s], acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[1][rt][s], B[0][s], acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0][rt][s], B[1][s], acc[rt], 0, 0, 0);
+        acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0][rt][s], B[0][s], acc[rt], 0, 0, 0);
+      }
+    }
+    const float cT = float(t.cos_Th[(col / d.n_Ph) % d.n_Th]);
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 16 * rt + 4 * lg + v;
+        if (row < d.n_r) {
+          const float val = cT * acc[rt][v];
+          if constexpr (ACCUM)
+            T[eb + row * M] = tv[rt * 4 + v] + val;
+          else
+            T[eb + row * M] = val;
+        }
+      }
+  }
+}
+
+template <int NRT, typename TI>
+void launch_t(const KDims& d, const KTab& t, const void* Y, float* T, bool accum, hipStream_t s) {
+  const int64_t ngroups = (d.M / 16) * d.n_eps;
+  int64_t blocks = (ngroups + 3) / 4;
+  const int64_t cap = int64_t(d.ncu) * 8;
+  if (blocks > cap) blocks = cap;
+  const TI* y = static_cast<const TI*>(Y);
+  if (accum)
+    k_radial_bf16x3<NRT, true, TI><<<unsigned(blocks), CB, 0, s>>>(d, t, y, T);
+  else
+    k_radial_bf16x3<NRT, false, TI><<<unsigned(blocks), CB, 0, s>>>(d, t, y, T);
+}
+
+template <typename TI>
+hipError_t launch_ti(const KDims& d, const KTab& t, const void* Y, float* T, bool accum, hipStream_t s) {
+  switch (t.NRP / 16) {
+    case 1: launch_t<1, TI>(d, t, Y, T, accum, s); break;
+    case 2: launch_t<2, TI>(d, t, Y, T, accum, s); break;
+    case 3: launch_t<3, TI>(d, t, Y, T, accum, s); break;
+    case 4: launch_t<4, TI>(d, t, Y, T, accum, s); break;
+    case 5: launch_t<5, TI>(d, t, Y, T, accum, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// round a double to bf16 (round to nearest even through FP32)
+uint16_t to_bf16(double x) {
+  float f = float(x);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+double from_bf16(uint16_t b) {
+  uint32_t u = uint32_t(b) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return double(f);
+}
+
+}  // namespace
+
+hipError_t launch_radial_bf16x3(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, bool accum,
+                                hipStream_t s) {
+  return y_f32 ? launch_ti<float>(d, t, Y, T, accum, s) : launch_ti<double>(d, t, Y, T, accum, s);
+}
+
+void build_radial_split(const HostTables& h, int n_r, std::vector<uint16_t>& out, int* KP3) {
+  const int NRP = h.NRP;
+  const int kp3 = ((n_r + 31) / 32) * 32;
+  *KP3 = kp3;
+  out.assign(size_t(3) * NRP * kp3, 0);
+  for (int i = 0; i < n_r; ++i)
+    for (int j = 0; j < n_r; ++j) {
+      double x = h.Dr[size_t(i) * n_r + j];
+      for (int p = 0; p < 3; ++p) {
+        const uint16_t b = to_bf16(x);
+        out[(size_t(p) * NRP + i) * kp3 + j] = b;
+        x -= from_bf16(b);
+      }
+    }
+}

@@ -37,8 +37,8 @@ struct KTab {
   const double* qN;          // [n_r * n_th * n_Th] weights of the particle number
   const double* qJ;          // [n_th * n_Th] weights of the boundary flux (without r^2)
   // mixed precision copies
-  const float* Dsplit;       // bf16x3 split of Dpad as 3 float planes [3][NRP][KP]
-  int KP, NRP;
+  const uint16_t* Dsplit;    // bf16x3 split of the radial matrix, [3][NRP][KP3] (bf16 bits)
+  int KP, NRP, KP3;
 };
 
 struct KCoef {
@@ -75,19 +75,24 @@ std::string validate_desc(const sp6_desc& d, sp6_status* code);
 
 enum PlaneMode { PM_APPLY = 0, PM_RHS = 1, PM_STAGE = 2 };
 
+// Stage arguments of the plane pass.  Yin, T and ynext are FP64 on the FP64 path;
+// on the mixed path T and ynext are FP32 and Yin is FP64 (first stage, apply,
+// rhs) or FP32 (later stages).  Everything else is FP64.
 struct StageArgs {
   int mode;              // PlaneMode
-  const double* Yin;     // stage input (FP64 path)
-  const double* T;       // sum of the r, theta, phi terms of L Yin (may be null = 0)
+  const void* Yin;       // stage input
+  const void* T;         // sum of the r, theta, phi terms of L Yin (may be null = 0)
   double* out;           // PM_APPLY / PM_RHS output
-  // PM_STAGE: accdst = (acc_from_Y ? Yin : accsrc) + cb * k ; ynext = (ysrc ? ysrc : Yin) + cn * k
+  // PM_STAGE: accdst = (accsrc ? accsrc : Yin) + cb * k ; ynext = (ysrc ? ysrc : Yin) + cn * k
   const double* accsrc;
   double* accdst;
   double cb;
   const double* ysrc;
-  double* ynext;
+  void* ynext;
   double cn;
   uint32_t terms;        // bit 3 Theta, bit 4 Phi
+  int mixed;             // 0: FP64 path; 1: mixed path
+  int yin_f32;           // mixed path: Yin is FP32
 };
 
 hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
@@ -127,12 +132,13 @@ hipError_t launch_diag(const KDims& d, const KTab& t, const double* F, double* p
 size_t diag_partial_count(const KDims& d);
 hipError_t launch_outflux(const KDims& d, const KTab& t, const double* F, double* j, hipStream_t s);
 
-// mixed precision (FP32 stage copies, bf16x3 radial MFMA)
-struct MixedBufs {
-  float* Yf;   // FP32 stage input
-  float* Tf;   // FP32 r/theta/phi terms
-};
-hipError_t launch_mixed_stage(const KDims& d, const KTab& t, const KCoef& c, int stage,
-                              double* y, double* acc, MixedBufs& b, double dt, hipStream_t s);
-hipError_t launch_mixed_apply(const KDims& d, const KTab& t, const KCoef& c, int mode,
-                              const double* F, double* out, MixedBufs& b, hipStream_t s);
+// mixed precision: FP32 column passes (input FP64 or FP32, T in FP32) and the
+// split-bf16 radial MFMA pass
+hipError_t launch_phi_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, bool accum,
+                            hipStream_t s);
+hipError_t launch_theta_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, bool accum,
+                              hipStream_t s);
+hipError_t launch_radial_bf16x3(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, bool accum,
+                                hipStream_t s);
+// host: split of the padded radial matrix into three bf16 planes [3][NRP][KP3]
+void build_radial_split(const HostTables& h, int n_r, std::vector<uint16_t>& out, int* KP3);
