@@ -165,6 +165,12 @@ sp6_status sp6_diagnostics(sp6_grid grid, const double* F, double* N, double* J_
  * cos(Theta_i) > 0 and Phi_m of w_i (2 pi / n_Phi) cos(Theta_i) F. */
 sp6_status sp6_outgoing_flux(sp6_grid grid, const double* F, double* j);
 
+/* Transpose of sp6_outgoing_flux (for the gradient of a flux loss): out is a
+ * device state array, zero everywhere except at r_out, where
+ * out[eps][theta][phi][i][m] = jbar[eps][theta][phi] w_i (2 pi / n_Phi) cos(Theta_i)
+ * for cos(Theta_i) > 0 (and 0 otherwise).  jbar: device [n_eps][n_theta][n_phi]. */
+sp6_status sp6_outgoing_flux_T(sp6_grid grid, const double* jbar, double* out);
+
 /* Bytes of device memory the handle currently holds. */
 sp6_status sp6_device_bytes(sp6_grid grid, size_t* bytes);
 

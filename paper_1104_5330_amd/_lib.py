@@ -20,7 +20,7 @@ SYMBOLS = [
     "sp6_get_nodes", "sp6_get_weights", "sp6_set_coefficients", "sp6_set_inflow",
     "sp6_project_inflow", "sp6_apply_L", "sp6_apply_L_terms", "sp6_apply_LT", "sp6_rhs",
     "sp6_step", "sp6_step_timed", "sp6_adjoint_step", "sp6_apply_filter", "sp6_diagnostics",
-    "sp6_outgoing_flux", "sp6_device_bytes",
+    "sp6_outgoing_flux", "sp6_outgoing_flux_T", "sp6_device_bytes",
 ]
 
 
@@ -76,6 +76,7 @@ def load():
         "sp6_apply_filter": (S, [P, P]),
         "sp6_diagnostics": (S, [P, P, dp, dp, dp]),
         "sp6_outgoing_flux": (S, [P, P, P]),
+        "sp6_outgoing_flux_T": (S, [P, P, P]),
         "sp6_device_bytes": (S, [P, ctypes.POINTER(ctypes.c_size_t)]),
     }
     for name, (res, args) in sig.items():

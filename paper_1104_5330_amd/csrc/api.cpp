@@ -696,6 +696,17 @@ sp6_status sp6_outgoing_flux(sp6_grid g, const double* F, double* j) {
   return SP6_OK;
 }
 
+sp6_status sp6_outgoing_flux_T(sp6_grid g, const double* jbar, double* out) {
+  if (sp6_status s = check_grid(g)) return s;
+  const size_t jb = size_t(g->d.n_eps) * g->d.n_th * g->d.n_ph * sizeof(double);
+  if (sp6_status s = check_dev(jbar, jb, "jbar")) return s;
+  if (sp6_status s = check_dev(out, state_bytes(g), "out")) return s;
+  if (sp6_status s = check_distinct(jbar, "jbar", out, "out", jb, state_bytes(g))) return s;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(launch_outflux_T(g->d, g->t, jbar, out, g->stream), "outgoing flux transpose");
+  return SP6_OK;
+}
+
 sp6_status sp6_device_bytes(sp6_grid g, size_t* bytes) {
   if (sp6_status s = check_grid(g)) return s;
   if (!bytes) return fail(SP6_ERR_ARG, "bytes is NULL");

@@ -94,7 +94,30 @@ __global__ __launch_bounds__(256) void k_outflux(KDims d, KTab t, const double* 
   if (lane == 0) jmap[w] = s;
 }
 
+// Transpose of k_outflux: out = 0 except at r_out, where
+// out(eps, theta, phi, Theta_i, Phi_m) = jbar(eps, theta, phi) * wflux_i.
+__global__ __launch_bounds__(256) void k_outflux_T(KDims d, KTab t, const double* __restrict__ jbar,
+                                                   double* __restrict__ out) {
+  const int64_t gid = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (gid >= d.P) return;
+  const int64_t e = gid / (d.n_r * d.M);
+  const int64_t rest = gid % (d.n_r * d.M);
+  const int j = int(rest / d.M);
+  const int64_t w = rest % d.M;  // (theta, phi, Theta, Phi)
+  double v = 0.0;
+  if (j == d.n_r - 1) {
+    const int iTh = int((w % d.plane) / d.n_Ph);
+    v = jbar[e * (d.M / d.plane) + w / d.plane] * t.wflux[iTh];
+  }
+  out[gid] = v;
+}
+
 }  // namespace
+
+hipError_t launch_outflux_T(const KDims& d, const KTab& t, const double* jbar, double* out, hipStream_t s) {
+  k_outflux_T<<<unsigned((d.P + 255) / 256), 256, 0, s>>>(d, t, jbar, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_project(const KDims& d, const KTab& t, const KCoef& c, double* F, hipStream_t s) {
   const int64_t n = 2 * int64_t(d.n_eps) * d.n_th * d.n_ph * d.plane;

@@ -131,6 +131,7 @@ hipError_t launch_diag(const KDims& d, const KTab& t, const double* F, double* p
                        double r_out2, double* out3, hipStream_t s);
 size_t diag_partial_count(const KDims& d);
 hipError_t launch_outflux(const KDims& d, const KTab& t, const double* F, double* j, hipStream_t s);
+hipError_t launch_outflux_T(const KDims& d, const KTab& t, const double* jbar, double* out, hipStream_t s);
 
 // mixed precision: FP32 column passes (input FP64 or FP32, T in FP32) and the
 // split-bf16 radial MFMA pass

@@ -182,3 +182,9 @@ class Sp6Grid:
         out = torch.empty(s, dtype=torch.float64, device=self.device) if out is None else out
         self._call(self.lib.sp6_outgoing_flux, _ptr(F, "F", self.shape), _ptr(out, "j", s))
         return out
+
+    def outgoing_flux_T(self, jbar, out=None):
+        s = (self.shape[0], self.shape[2], self.shape[3])
+        out = self.empty() if out is None else out
+        self._call(self.lib.sp6_outgoing_flux_T, _ptr(jbar, "jbar", s), _ptr(out, "out", self.shape))
+        return out
