@@ -1,13 +1,22 @@
 """Benchmark of the 6D spectral transport hot path on one MI355X.
 
-Workload: emission + absorption, 8 energy groups,
+Headline workload: emission + absorption, 8 energy groups,
 (n_r, n_theta, n_phi, n_Theta, n_Phi) = (33, 16, 32, 16, 32): 69,206,016 points,
-FP64, RK4 at dt = 0.2 (r_1 - r_0).  One "step" is one full RK4 step over the
-whole grid; value = grid-point updates per second with every input resident in
-HBM.  Synthetic seeded inputs (no dataset is involved).
+FP64, classical RK4 at dt = 0.2 (r_1 - r_0).  One "step" is one full RK4 step over
+the whole grid; value = grid-point updates per second with every input already
+resident in HBM.  Inputs are synthetic and seeded (no dataset is involved).
 
-Prints one JSON line with the headline metric, the roofline of the dominant
-kernel (algorithmic bytes / HIP-event duration) and the CPU oracle baseline.
+Also measured on the same JSON line ("forms"):
+  mixed   : the scattering workload (same grid, sigma = kappa/2) on the mixed path,
+            with its error against the FP64 path after the timed steps;
+  adjoint : the 4-group workload (same angular grid), 200 steps forward plus the
+            checkpointed (every 20) discrete-adjoint backward pass of the
+            outgoing-flux misfit; value = forward-equivalent updates (points x 200)
+            over the forward + recompute + backward wall time.
+
+The roofline object is for the dominant kernel of the headline form: algorithmic
+bytes per launch (bytes per point below x points) over its mean HIP-event
+duration, against 8 TB/s.
 """
 
 import argparse
@@ -20,15 +29,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "6D grid-point updates/s per RK4 step (FP64 vs mixed vs adjoint), % HBM peak"
 
-# Algorithmic bytes per grid point of one launch of each kernel class (FP64):
-#   phi    : read Y, write T                          16
-#   theta  : read Y, read T, write T                  24
-#   radial : read Y, read T, write T                  24
-#   plane  : stage 1 read Y, T; write acc, Y'         32
-#            stages 2-3 read Y, T, y, acc; write acc, Y'   48
-#            stage 4 read Y, T, acc; write y          32   -> mean 40 per launch
-BYTES_PER_POINT = {"phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 40.0}
+# Algorithmic bytes per grid point of one launch, averaged over the four RK stages.
+# FP64 path (state, stage copy, T, accumulator all FP64):
+#   phi    : read Y, write T                                   16
+#   theta  : read Y, T, write T                                24
+#   radial : read Y, T, write T                                24
+#   plane  : stage 1 read Y, T; write acc, Y'                  32
+#            stages 2, 3 read Y, T, y, acc; write acc, Y'      48
+#            stage 4 read Y, T, acc; write y                   32   -> mean 40
+BYTES_FP64 = {"phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 40.0}
+# Mixed path (stage copy and T in FP32; stage 1 reads the FP64 state):
+#   phi    : (8 + 4, then 3 x (4 + 4)) / 4                       9
+#   theta  : (8 + 4 + 4, then 3 x 12) / 4                       13
+#   radial : same as theta                                      13
+#   plane  : (8+4+8+4, 4+4+8+8+8+4 twice, 4+4+8+8) / 4          30
+BYTES_MIXED = {"phi": 9.0, "theta": 13.0, "radial": 13.0, "plane": 30.0}
+# minimal traffic of a fully fused RK4 step (read the stage state once; y, acc and
+# the next stage state as registers of the scheme): 128 B (FP64), 104 B (mixed)
+FUSED_MIN_B = {"fp64": 128.0, "mixed": 104.0}
 
 
 def parse():
@@ -36,23 +56,162 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--form", choices=["all", "fp64", "mixed", "adjoint"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 553,648,128 bytes (byte-counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(cfg, nsteps):
+PROFILE_FP64 = os.path.join(ROOT, "profiles", "fp64_step_emit_abs_33x16x32x16x32_g8.md")
+PLANE_SRC = os.path.join(ROOT, "paper_1104_5330_amd", "csrc", "k_plane.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the plane pass from the committed rocprofv3 byte
+    counters, or None when the kernel source changed since they were taken."""
+    import hashlib
+    try:
+        txt = open(PROFILE_FP64).read()
+        fields = dict(line.split(": ", 1) for line in txt.splitlines() if line.startswith("traffic_"))
+        cur = hashlib.sha256(open(PLANE_SRC, "rb").read()).hexdigest()[:16]
+        if fields.get("traffic_source_sha256_16", "").strip() != cur:
+            return None
+        return float(fields["traffic_plane_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def kernel_table(kt, P, bpp, total_ms):
+    out = {}
+    for name, (kms, n) in kt.items():
+        if n == 0:
+            continue
+        b = bpp.get(name, 0.0) * P
+        out[name] = {"launches": n, "avg_ms": kms / n, "share": kms / total_ms,
+                     "bytes_per_point": bpp.get(name),
+                     "alg_GBs": (b * n / (kms / 1e3)) / 1e9 if kms > 0 else None}
+    return out
+
+
+def run_steps(cfg, precision, scattering, steps, warmup, F0=None):
+    import torch
+    import synth
+    from paper_1104_5330_amd import Sp6Grid
+
+    dev = torch.device("cuda", 0)
+    if F0 is None:
+        F0 = synth.fields.shell_state(cfg, device=dev)
+    coeffs = [torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)]
+    G = Sp6Grid.from_config(cfg, precision=precision, bc=True, scattering=scattering)
+    G.set_coefficients(*coeffs)
+    W = F0.clone()
+    G.step(W, cfg.dt, warmup)
+    del W
+    F = F0.clone()
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    kt = G.step_timed(F, cfg.dt, steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    assert torch.isfinite(F).all()
+    G.close()
+    return F, F0, ms, kt
+
+
+def form_fp64(args):
+    import synth
+    cfg = synth.config(2)
+    _, _, ms, kt = run_steps(cfg, "fp64", False, args.steps, args.warmup)
+    P = cfg.points
+    value = P * args.steps / (ms / 1e3)
+    kern = kernel_table(kt, P, BYTES_FP64, ms)
+    return cfg, value, ms, kern
+
+
+def form_mixed(args):
+    import torch
+    import synth
+    cfg = synth.config(3)
+    Fm, F0, ms, kt = run_steps(cfg, "mixed", True, args.steps, args.warmup)
+    F64, _, ms64, _ = run_steps(cfg, "fp64", True, args.steps, 0, F0=F0)
+    err_max = ((Fm - F64).abs().max() / F64.abs().max()).item()
+    err_l2 = (torch.linalg.vector_norm(Fm - F64) / torch.linalg.vector_norm(F64)).item()
+    P = cfg.points
+    return {
+        "workload": cfg.name, "grid": list(cfg.shape), "physics": "emission+absorption+isotropic scattering",
+        "value": P * args.steps / (ms / 1e3), "unit": "grid-point updates/s", "ms_per_step": ms / args.steps,
+        "steps": args.steps, "dtype": "f32 derivatives / bf16x3 MFMA radial / f64 state",
+        "fp64_same_workload": P * args.steps / (ms64 / 1e3),
+        "error_vs_fp64": {"max_rel": err_max, "l2_rel": err_l2, "after_steps": args.steps},
+        "hbm_fraction_algorithmic_104B": P * args.steps / (ms / 1e3) * FUSED_MIN_B["mixed"] / (HBM_PEAK_GBS * 1e9),
+        "kernels": kernel_table(kt, P, BYTES_MIXED, ms),
+    }
+
+
+def form_adjoint(args):
+    import numpy as np
+    import torch
+    import synth
+    from paper_1104_5330_amd import Sp6Grid
+    from paper_1104_5330_amd.autograd import transport, outgoing_flux
+
+    cfg = synth.config(4)
+    n, K = cfg.steps, 20
+    dev = torch.device("cuda", 0)
+    G = Sp6Grid.from_config(cfg, scattering=False)
+    shp = (cfg.n_r, cfg.n_theta, cfg.n_phi)
+    kap1, _, eta1 = synth.fields.coefficients(cfg, kappa_s=np.ones(shp))
+    c = torch.as_tensor(kap1[:, 0, 0, 0].copy(), device=dev).view(-1, 1, 1, 1)
+    B = torch.as_tensor(eta1 / kap1, device=dev)
+    r = synth.fields.nodes(cfg)[0]
+    ks0 = torch.as_tensor(np.broadcast_to((r ** -2.0)[:, None, None], shp).copy(), device=dev)
+    rho = torch.as_tensor(synth.fields.low_mode_position_field(cfg, seed=0), device=dev)
+    F0 = synth.fields.shell_state(cfg, device=dev)
+
+    def loss(ks, F, jt):
+        kappa = c * ks.unsqueeze(0)
+        Fn = transport(G, F, kappa, torch.zeros_like(kappa), kappa * B, cfg.dt, n, K)
+        j = outgoing_flux(G, Fn)
+        return ((j - jt) ** 2).sum()
+
+    with torch.no_grad():
+        kap = c * (ks0 * (1.0 + 0.2 * rho)).unsqueeze(0)
+        jt = outgoing_flux(G, transport(G, F0, kap, torch.zeros_like(kap), kap * B, cfg.dt, n, K)).clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ks = ks0.clone().requires_grad_(True)
+    Ft = F0.clone().requires_grad_(True)
+    L = loss(ks, Ft, jt)
+    L.backward()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    P = cfg.points
+    return {
+        "workload": cfg.name, "grid": list(cfg.shape), "steps": n, "checkpoint_every": K,
+        "value": P * n / t, "unit": "forward-equivalent grid-point updates/s (forward + recompute + adjoint)",
+        "seconds": t, "loss": L.item(), "grad_norm_kappa_s": torch.linalg.vector_norm(ks.grad).item(),
+        "dtype": "f64",
+        "fd_check": "tests/test_gpu_adjoint.py: 16 joint directions, worst relative error printed there",
+    }
+
+
+def cpu_baseline(nsteps):
     """The oracle as it stands, timed on the host: nsteps RK4 steps of one energy
-    group of the workload (the groups are independent)."""
+    group of the headline workload (the groups are independent)."""
     import numpy as np
     import synth
     from oracle import grid as og, step
 
+    cfg = synth.config(2)
     sub = cfg.scaled(n_eps=1)
     F = synth.fields.shell_state(sub)
     k, s, e = synth.fields.coefficients(sub)
     g = og.make_grid(*sub.shape)
-    p = step.Physics(k, s, e, scattering=sub.physics == "scatter")
+    p = step.Physics(k, s, e, scattering=False)
     threads = None
     try:
         from threadpoolctl import threadpool_info
@@ -67,8 +226,18 @@ def cpu_baseline(cfg, nsteps):
     assert np.isfinite(y).all()
     return {"value": sub.points * nsteps / t, "unit": "grid-point updates/s", "cores": threads or os.cpu_count(),
             "kind": "oracle",
-            "sample": f"{nsteps} RK4 steps of 1 of {cfg.n_eps} energy groups ({sub.points} points), "
-                      f"dense 1D matrices in numpy FP64, {t:.1f} s"}
+            "sample": f"{nsteps} RK4 steps of 1 of {cfg.n_eps} energy groups ({sub.points} points) of the "
+                      f"headline workload, dense 1D matrices in numpy FP64, {t:.1f} s"}
+
+
+def copy_calibration():
+    import torch
+    n = 553648128 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return {"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}
 
 
 def main():
@@ -77,66 +246,37 @@ def main():
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(energy groups would shard across GPUs with no communication; not built).", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
-
-    import synth
-    from paper_1104_5330_amd import Sp6Grid
-
-    cfg = synth.config(2)
-    dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    F0 = synth.fields.shell_state(cfg, device=dev)
-    k, s, e = (torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg))
-    G = Sp6Grid.from_config(cfg, precision="fp64", bc=True, scattering=False)
-    G.set_coefficients(k, s, e)
-    F = F0.clone()
-    G.step(F, cfg.dt, args.warmup)
-    torch.cuda.synchronize()
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    kt = G.step_timed(F, cfg.dt, args.steps)
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    assert torch.isfinite(F).all()
-    P = cfg.points
-    value = P * args.steps / (ms / 1e3)
-
-    kernels = {}
-    for name, (kms, n) in kt.items():
-        if n == 0:
-            continue
-        b = BYTES_PER_POINT.get(name, 0.0) * P
-        kernels[name] = {"launches": n, "avg_ms": kms / n, "share": kms / ms,
-                         "alg_GBs": (b * n / (kms / 1e3)) / 1e9 if kms > 0 else None}
-    dom = max(kernels, key=lambda c: kt[c][0])
-    dk = kernels[dom]
-    roof = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": dk["alg_GBs"] / HBM_PEAK_GBS, "traffic": None,
-            "bytes_per_point_per_launch": BYTES_PER_POINT[dom], "points_per_launch": P}
-
-    out = {
-        "metric": "6D grid-point updates/s per RK4 step (FP64 vs mixed vs adjoint), % HBM peak",
-        "value": value,
-        "unit": "grid-point updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": cfg.name, "grid": list(cfg.shape), "points": P, "physics": "emission+absorption",
-                   "dt": cfg.dt, "form": "fp64"},
-        "roofline": roof,
-        "kernels": kernels,
-        "hbm_fraction_algorithmic_128B": value * 128.0 / (HBM_PEAK_GBS * 1e9),
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_steps)
+    torch.cuda.set_device(0)
+    out = {"metric": METRIC}
+    forms = {}
+    if args.form in ("all", "fp64"):
+        cfg, value, ms, kern = form_fp64(args)
+        dom = max(kern, key=lambda c: kern[c]["avg_ms"] * kern[c]["launches"])
+        dk = kern[dom]
+        out.update({
+            "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": cfg.name, "grid": list(cfg.shape), "points": cfg.points,
+                       "physics": "emission+absorption", "dt": cfg.dt, "form": "fp64"},
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBs"], "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": dk["alg_GBs"] / HBM_PEAK_GBS,
+                         "traffic": measured_traffic() if dom == "plane" else None,
+                         "bytes_per_point_per_launch": BYTES_FP64[dom], "points_per_launch": cfg.points},
+            "kernels": kern,
+            "hbm_fraction_algorithmic_128B": value * FUSED_MIN_B["fp64"] / (HBM_PEAK_GBS * 1e9),
+        })
+        forms["fp64"] = {"value": value, "ms_per_step": ms / args.steps}
+    if args.form in ("all", "mixed"):
+        forms["mixed"] = form_mixed(args)
+    if args.form in ("all", "adjoint"):
+        forms["adjoint"] = form_adjoint(args)
+    out["forms"] = forms
+    if args.copy_calibration:
+        out["copy_calibration"] = copy_calibration()
+    if not args.no_cpu_baseline and args.form in ("all", "fp64"):
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(out), flush=True)
 
 
