@@ -23,8 +23,8 @@ namespace {
 
 constexpr int CB = 256;  // threads per block of the column kernels
 
-__constant__ double c_lines[2 * LINE_TAB_SIZE];
-__constant__ float c_lines_f[2 * LINE_TAB_SIZE];  // FP32 copy for the mixed path
+__constant__ double c_lines[LINE_TAB_KINDS * LINE_TAB_SIZE];
+__constant__ float c_lines_f[LINE_TAB_KINDS * LINE_TAB_SIZE];  // FP32 copy for the mixed path
 
 template <int L, typename TC = double>
 SP6_DEV const TC* line_tab(int kind) {
@@ -396,9 +396,9 @@ hipError_t launch_filter_columns(const KDims& d, const KTab& t, double* F, hipSt
 }
 
 hipError_t init_line_tables_columns(const double* tab) {
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * LINE_TAB_KINDS * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
-  float f[2 * LINE_TAB_SIZE];
-  for (int i = 0; i < 2 * LINE_TAB_SIZE; ++i) f[i] = float(tab[i]);
+  static float f[LINE_TAB_KINDS * LINE_TAB_SIZE];
+  for (int i = 0; i < LINE_TAB_KINDS * LINE_TAB_SIZE; ++i) f[i] = float(tab[i]);
   return hipMemcpyToSymbol(HIP_SYMBOL(c_lines_f), f, sizeof f, 0, hipMemcpyHostToDevice);
 }

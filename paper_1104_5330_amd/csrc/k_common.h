@@ -54,7 +54,40 @@ constexpr int line_tab_offset(int L) {
   return L == 4 ? 0 : L == 8 ? 8 : L == 16 ? 40 : L == 32 ? 168 : L == 64 ? 680 : -1;
 }
 constexpr int LINE_TAB_SIZE = 2728;  // sum of 2 (L/2)^2 over L = 4 .. 64
-enum { LT_DERIV = 0, LT_FILTER = 1 };
+constexpr int LINE_TAB_KINDS = 4;
+// 0: derivative, 1: filter, 2 and 3: the same transposed (entries of consecutive
+// output pairs at one input index j contiguous)
+enum { LT_DERIV = 0, LT_FILTER = 1, LT_DERIV_T = 2, LT_FILTER_T = 3 };
+
+// Output pairs i0 .. i0 + NPAIR - 1 of a centro-(anti)symmetric L x L matrix
+// applied to a line that is read element by element through ld(q) (from LDS):
+// the line is streamed once (e_j, o_j formed on the fly) and only the 2 NPAIR
+// accumulators stay live.  tabT is the transposed even/odd table.
+template <int L, int NPAIR, bool ANTI, typename T, typename TT, typename Load, typename Emit>
+SP6_DEV void eo_pairs_stream(const TT* __restrict__ tabT, int i0, Load&& ld, Emit&& emit) {
+  constexpr int h = L / 2;
+  T p[NPAIR], q[NPAIR];
+#pragma unroll
+  for (int ii = 0; ii < NPAIR; ++ii) p[ii] = q[ii] = T(0);
+  // partial unrolling bounds the number of line elements the compiler hoists
+#pragma unroll 4
+  for (int j = 0; j < h; ++j) {
+    const T a = ld(j), b = ld(L - 1 - j);
+    const T e = a + b, o = a - b;
+    const TT* __restrict__ At = tabT + j * h + i0;
+    const TT* __restrict__ Bt = tabT + h * h + j * h + i0;
+#pragma unroll
+    for (int ii = 0; ii < NPAIR; ++ii) {
+      p[ii] = fma(T(At[ii]), e, p[ii]);
+      q[ii] = fma(T(Bt[ii]), o, q[ii]);
+    }
+  }
+#pragma unroll
+  for (int ii = 0; ii < NPAIR; ++ii) {
+    emit(i0 + ii, p[ii] + q[ii]);
+    emit(L - 1 - (i0 + ii), ANTI ? (q[ii] - p[ii]) : (p[ii] - q[ii]));
+  }
+}
 
 // inflow node test (Sect. 4.2): r_in with cos(Theta) > 0, r_out with cos(Theta) < 0
 SP6_DEV bool is_inflow(const KDims& d, const KTab& t, int j, int iTh) {

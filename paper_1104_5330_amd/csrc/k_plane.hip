@@ -14,8 +14,8 @@
 
 namespace {
 
-__constant__ double c_lines[2 * LINE_TAB_SIZE];
-__constant__ float c_lines_f[2 * LINE_TAB_SIZE];  // FP32 copy for the mixed path
+__constant__ double c_lines[LINE_TAB_KINDS * LINE_TAB_SIZE];
+__constant__ float c_lines_f[LINE_TAB_KINDS * LINE_TAB_SIZE];  // FP32 copy for the mixed path
 
 template <int L, typename TC = double>
 SP6_DEV const TC* line_tab(int kind) {
@@ -141,27 +141,38 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
   const TO* Tin = static_cast<const TO*>(a.T);
   TO* ynext = static_cast<TO*>(a.ynext);
 
-  TY yin[C::PPT];
-  TO tv[C::PPT];
-  double av[NA ? C::PPT : 1], yv[NY ? C::PPT : 1];
-  // each workgroup walks one contiguous range of plane groups
+  // each workgroup walks one contiguous range of plane groups; every global
+  // operand of the next group is loaded one iteration ahead (register double
+  // buffering), so its loads are in flight during the lines and the epilogue
   const int per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
   const int gbeg = per_blk * blockIdx.x, gend = min(ngroups, gbeg + per_blk);
-  auto load = [&](int g, TY* yi, TO* ti, double* ai, double* yo) {
+  auto load_y = [&](int g, TY* yi) {
+    const int plane0 = g * C::NPW;
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      const int p = tid + q * C::NTHR;
+      const bool ok = g < gend && plane0 + p / C::PLANE < npl;
+      yi[q] = ok ? Yin[int64_t(plane0) * C::PLANE + p] : TY(0);
+    }
+  };
+  auto load_rest = [&](int g, TO* ti, double* ai, double* yo) {
     const int plane0 = g * C::NPW;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int p = tid + q * C::NTHR;
       const bool ok = g < gend && plane0 + p / C::PLANE < npl;
       const int64_t gp = int64_t(plane0) * C::PLANE + p;
-      yi[q] = ok ? Yin[gp] : TY(0);
       ti[q] = (ok && needT) ? Tin[gp] : TO(0);
       if constexpr (NA) ai[q] = ok ? a.accsrc[gp] : 0.0;
       if constexpr (NY) yo[q] = ok ? a.ysrc[gp] : 0.0;
     }
   };
+  TY yin[C::PPT];
+  TO tn[C::PPT];
+  double an[NA ? C::PPT : 1], yn[NY ? C::PPT : 1];
   int grp = gbeg;
-  load(grp, yin, tv, av, yv);
+  load_y(grp, yin);
+  load_rest(grp, tn, an, yn);
   for (; grp < gend; ++grp) {
     const int plane0 = grp * C::NPW;
 #pragma unroll
@@ -182,10 +193,16 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       sPl[tid] = pi;
     }
     __syncthreads();
-    TY nyin[C::PPT];
-    TO ntv[C::PPT];
-    double nav[NA ? C::PPT : 1], nyv[NY ? C::PPT : 1];
-    load(grp + 1, nyin, ntv, nav, nyv);
+    TO tv[C::PPT];
+    double av[NA ? C::PPT : 1], yv[NY ? C::PPT : 1];
+#pragma unroll
+    for (int q = 0; q < C::PPT; ++q) {
+      tv[q] = tn[q];
+      if constexpr (NA) av[q] = an[q];
+      if constexpr (NY) yv[q] = yn[q];
+    }
+    load_y(grp + 1, yin);
+    load_rest(grp + 1, tn, an, yn);
 
     {  // line phase
       const int lane = tid & 63;
@@ -194,9 +211,6 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       const bool isTh = li < NT;
       const LineMap<NT> lm = line_map<NT>(pl, li);
       const double inv_r = sPl[pl].inv_r, cot_th = sPl[pl].cot_th;
-      TC v[C::L];
-#pragma unroll
-      for (int q = 0; q < C::L; ++q) v[q] = TC(sY[lm.idx(q)]);
       if (d.scattering && a.mode != PM_APPLY && part == 0) {
         // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
         double s = 0.0;
@@ -210,10 +224,11 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
         if (li == NT) sPl[pl].mean = s;
       }
       TC* out = sR[isTh ? 0 : 1];
-      eo_split<C::L>(v);
-      eo_pairs<C::L, C::PPW, true>(line_tab<C::L, TC>(LT_DERIV), part * C::PPW, v, [&](int q, TC z) {
-        out[lm.idx(q)] = TC(line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh)) * z;
-      });
+      // the line is streamed from LDS against the transposed table instead of
+      // being held in registers: fewer registers, higher occupancy
+      eo_pairs_stream<C::L, C::PPW, true, TC>(
+          line_tab<C::L, TC>(LT_DERIV_T), part * C::PPW, [&](int q) { return TC(sY[lm.idx(q)]); },
+          [&](int q, TC z) { out[lm.idx(q)] = TC(line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh)) * z; });
     }
     __syncthreads();
 
@@ -245,13 +260,6 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       if constexpr (NY) yb = yv[q];
       if (a.accdst) a.accdst[gp] = ab + a.cb * k;
       if (ynext) ynext[gp] = TO(yb + a.cn * k);
-    }
-#pragma unroll
-    for (int q = 0; q < C::PPT; ++q) {
-      yin[q] = nyin[q];
-      tv[q] = ntv[q];
-      if constexpr (NA) av[q] = nav[q];
-      if constexpr (NY) yv[q] = nyv[q];
     }
     __syncthreads();
   }
@@ -314,10 +322,6 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
     const int64_t pid = plane0 + pl;
     const PlaneIdx pi = plane_index(d, pid < npl ? pid : 0);
     const double inv_r = t.inv_r[pi.j], cot_th = t.cot_th[pi.l];
-    double v[C::L];
-#pragma unroll
-    for (int q = 0; q < C::L; ++q)
-      v[q] = line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh) * sU[lm.idx(q)];
     if (part == 0 && !isTh && !lt) {
       const int i = li - NT;
       double su = 0.0, suy = 0.0, sy = 0.0;
@@ -334,8 +338,10 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
       sRed[pl * NT + i][2] = t.wmean[i] * sy;
     }
     double* out = sR[isTh ? 0 : 1];
-    eo_split<C::L>(v);
-    eo_pairs<C::L, C::PPW, true>(line_tab<C::L>(LT_DERIV), part * C::PPW, v, [&](int q, double z) { out[lm.idx(q)] = -z; });
+    eo_pairs_stream<C::L, C::PPW, true, double>(
+        line_tab<C::L>(LT_DERIV_T), part * C::PPW,
+        [&](int q) { return line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh) * sU[lm.idx(q)]; },
+        [&](int q, double z) { out[lm.idx(q)] = -z; });
   }
   __syncthreads();
 
@@ -407,21 +413,15 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_filter_plane(KDims d, KTab t, 
   const int pl = lane / C::LPP, li = lane % C::LPP;
   const bool isTh = li < NT;
   const LineMap<NT> lm = line_map<NT>(pl, li);
-  if (isTh) {
-    double v[C::L];
-#pragma unroll
-    for (int q = 0; q < C::L; ++q) v[q] = sY[lm.idx(q)];
-    eo_split<C::L>(v);
-    eo_pairs<C::L, C::PPW, false>(line_tab<C::L>(LT_FILTER), part * C::PPW, v, [&](int q, double z) { sR[lm.idx(q)] = z; });
-  }
+  if (isTh)
+    eo_pairs_stream<C::L, C::PPW, false, double>(
+        line_tab<C::L>(LT_FILTER_T), part * C::PPW, [&](int q) { return sY[lm.idx(q)]; },
+        [&](int q, double z) { sR[lm.idx(q)] = z; });
   __syncthreads();
-  if (!isTh) {
-    double v[C::L];
-#pragma unroll
-    for (int q = 0; q < C::L; ++q) v[q] = sR[lm.idx(q)];
-    eo_split<C::L>(v);
-    eo_pairs<C::L, C::PPW, false>(line_tab<C::L>(LT_FILTER), part * C::PPW, v, [&](int q, double z) { sY[lm.idx(q)] = z; });
-  }
+  if (!isTh)
+    eo_pairs_stream<C::L, C::PPW, false, double>(
+        line_tab<C::L>(LT_FILTER_T), part * C::PPW, [&](int q) { return sR[lm.idx(q)]; },
+        [&](int q, double z) { sY[lm.idx(q)] = z; });
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
@@ -525,9 +525,9 @@ hipError_t launch_filter_plane(const KDims& d, const KTab& t, double* F, hipStre
 }
 
 hipError_t init_line_tables_plane(const double* tab) {
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * 2 * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_lines), tab, sizeof(double) * LINE_TAB_KINDS * LINE_TAB_SIZE, 0, hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
-  float f[2 * LINE_TAB_SIZE];
-  for (int i = 0; i < 2 * LINE_TAB_SIZE; ++i) f[i] = float(tab[i]);
+  static float f[LINE_TAB_KINDS * LINE_TAB_SIZE];
+  for (int i = 0; i < LINE_TAB_KINDS * LINE_TAB_SIZE; ++i) f[i] = float(tab[i]);
   return hipMemcpyToSymbol(HIP_SYMBOL(c_lines_f), f, sizeof f, 0, hipMemcpyHostToDevice);
 }

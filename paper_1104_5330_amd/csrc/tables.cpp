@@ -82,11 +82,22 @@ std::vector<double> clenshaw_curtis(int n_r) {
 
 }  // namespace
 
+// Kinds 0/1: derivative and filter tables, A then B row major (A[i][j] at i h + j);
+// kinds 2/3: the same tables transposed (A[i][j] at j h + i), so that the
+// entries of consecutive output pairs at one j are contiguous.
 std::vector<double> build_line_tables() {
   std::vector<double> out;
-  for (int kind = 0; kind < 2; ++kind)
+  for (int kind = 0; kind < 4; ++kind)
     for (int L = 4; L <= 64; L *= 2) {
-      std::vector<double> ab = even_odd(kind == 0 ? fourier_matrix(L) : filter_matrix(L), L);
+      std::vector<double> ab = even_odd((kind % 2) == 0 ? fourier_matrix(L) : filter_matrix(L), L);
+      if (kind >= 2) {
+        const int h = L / 2;
+        std::vector<double> tr(ab.size());
+        for (int half = 0; half < 2; ++half)
+          for (int i = 0; i < h; ++i)
+            for (int j = 0; j < h; ++j) tr[size_t(half) * h * h + size_t(j) * h + i] = ab[size_t(half) * h * h + size_t(i) * h + j];
+        ab.swap(tr);
+      }
       out.insert(out.end(), ab.begin(), ab.end());
     }
   return out;
