@@ -33,19 +33,20 @@ METRIC = "6D grid-point updates/s per RK4 step (FP64 vs mixed vs adjoint), % HBM
 
 # Algorithmic bytes per grid point of one launch, averaged over the four RK stages.
 # FP64 path (state, stage copy, T, accumulator all FP64):
+#   thetaphi: theta and phi fused: read Y, write T             16
 #   phi    : read Y, write T                                   16
 #   theta  : read Y, T, write T                                24
 #   radial : read Y, T, write T                                24
 #   plane  : stage 1 read Y, T; write acc, Y'                  32
 #            stages 2, 3 read Y, T, y, acc; write acc, Y'      48
 #            stage 4 read Y, T, acc; write y                   32   -> mean 40
-BYTES_FP64 = {"phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 40.0}
+BYTES_FP64 = {"thetaphi": 16.0, "phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 40.0}
 # Mixed path (stage copy and T in FP32; stage 1 reads the FP64 state):
-#   phi    : (8 + 4, then 3 x (4 + 4)) / 4                       9
+#   thetaphi, phi : (8 + 4, then 3 x (4 + 4)) / 4                9
 #   theta  : (8 + 4 + 4, then 3 x 12) / 4                       13
 #   radial : same as theta                                      13
 #   plane  : (8+4+8+4, 4+4+8+8+8+4 twice, 4+4+8+8) / 4          30
-BYTES_MIXED = {"phi": 9.0, "theta": 13.0, "radial": 13.0, "plane": 30.0}
+BYTES_MIXED = {"thetaphi": 9.0, "phi": 9.0, "theta": 13.0, "radial": 13.0, "plane": 30.0}
 # minimal traffic of a fully fused RK4 step (read the stage state once; y, acc and
 # the next stage state as registers of the scheme): 128 B (FP64), 104 B (mixed)
 FUSED_MIN_B = {"fp64": 128.0, "mixed": 104.0}

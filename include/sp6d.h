@@ -140,8 +140,9 @@ sp6_status sp6_step(sp6_grid grid, double* F, double dt, int32_t nsteps);
  * first launch and after every kernel launch.  On return (the stream is
  * synchronised) kernel_ms[c] holds the summed duration and launches[c] the number
  * of launches of kernel class c: 0 phi pass, 1 theta pass, 2 radial pass, 3 plane
- * pass (Theta, Phi, collision, inflow, RK stage), 4 filter.  Both arrays are host
- * arrays of 5 entries.  For measurement only. */
+ * pass (Theta, Phi, collision, inflow, RK stage), 4 filter, 5 theta and phi
+ * passes fused into one (used when n_phi = 2 n_theta <= 32).  Both arrays are
+ * host arrays of 6 entries.  For measurement only. */
 sp6_status sp6_step_timed(sp6_grid grid, double* F, double dt, int32_t nsteps, double* kernel_ms,
                           int64_t* launches);
 

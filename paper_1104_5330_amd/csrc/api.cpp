@@ -150,7 +150,7 @@ struct Timer {
   }
 };
 
-enum { KC_PHI = 0, KC_THETA = 1, KC_RADIAL = 2, KC_PLANE = 3, KC_FILTER = 4, KC_COUNT = 5 };
+enum { KC_PHI = 0, KC_THETA = 1, KC_RADIAL = 2, KC_PLANE = 3, KC_FILTER = 4, KC_SPHERE = 5, KC_COUNT = 6 };
 
 hipError_t ensure(sp6_grid g, double** p, size_t n) {
   if (*p) return hipSuccess;
@@ -170,6 +170,13 @@ hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transp
   hipError_t e = hipSuccess;
   bool acc = false;
   const double sg = transpose ? -1.0 : 1.0;
+  if ((terms & 6u) == 6u && sphere_fusable(g->d, false)) {
+    e = launch_sphere(g->d, g->t, Y, g->T, sg, mask_in, in_scale, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
+    if (e != hipSuccess) return e;
+    acc = true;
+    terms &= ~6u;
+  }
   if (terms & 4u) {
     e = launch_phi(g->d, g->t, Y, g->T, acc, sg, mask_in, in_scale, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_PHI);
@@ -197,6 +204,13 @@ hipError_t column_terms_mixed(sp6_grid g, const void* Y, bool y_f32, uint32_t te
                               Timer* tm = nullptr) {
   hipError_t e = hipSuccess;
   bool acc = false;
+  if ((terms & 6u) == 6u && sphere_fusable(g->d, true)) {
+    e = launch_sphere_mixed(g->d, g->t, Y, y_f32, g->Tf, g->stream);
+    if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
+    if (e != hipSuccess) return e;
+    acc = true;
+    terms &= ~6u;
+  }
   if (terms & 4u) {
     e = launch_phi_mixed(g->d, g->t, Y, y_f32, g->Tf, acc, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_PHI);

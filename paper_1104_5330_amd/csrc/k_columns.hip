@@ -267,6 +267,125 @@ __global__ __launch_bounds__(CB) void k_filter_theta(KDims d, KTab t, double* __
   });
 }
 
+// ---------------------------------------------------------------------------
+// theta and phi terms together.  One workgroup takes one (eps, r) slab restricted
+// to a tile of CW in-plane columns that is closed under the DFS partner map
+// c -> c' (Phi_m -> Phi_m + pi): with all n_theta x n_phi values of each of its
+// columns, every phi line and every theta DFS line of the tile lies inside it.
+// The tile is staged once in LDS; half of the threads take the phi lines (one
+// theta row and column each), the other half the theta DFS lines (one phi index
+// below n_phi / 2 and column each, partner column c' at phi + pi).  Both lines
+// have length n_phi = 2 n_theta.  The theta results go back through LDS to the
+// phi threads, which add their own and store T: the state is read once and T
+// written once.
+//
+// Tile columns: with R = min(CW / 2, n_Phi / 2), tile column col is in-plane
+// column cbase + (col mod R) + [col & R] n_Phi / 2 + (col div 2R) n_Phi, and its
+// partner is col ^ R.  For R < n_Phi / 2 a tile is two runs of R columns of one
+// Theta row, m0 .. m0 + R - 1 and their partners; otherwise whole Theta rows.
+
+template <int NTH, int CW, typename TC>
+struct SPC {
+  static constexpr int NPH = 2 * NTH;
+  static constexpr int L = NPH;                        // phi line = theta DFS line
+  static constexpr int NL = NTH * CW;                  // phi lines = theta lines
+  static constexpr int NTHR = 2 * NL < 64 ? 64 : 2 * NL;
+  static constexpr int NE = NTH * NPH * CW;            // values per tile
+  static constexpr int EPT = (NE + NTHR - 1) / NTHR;   // staged values per thread
+  static_assert(NTHR % CW == 0, "a thread keeps its tile column while staging");
+  static_assert(NE * sizeof(TC) <= 65536, "tile exceeds the LDS budget");
+};
+
+// TI: stored type of the input; TC: compute type and stored type of T
+template <int NTH, int CW, typename TI, typename TC>
+__global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KTab t, const TI* __restrict__ Y,
+                                                                   TC* __restrict__ T, double coef_sign,
+                                                                   int mask_in, double in_scale, int ntiles) {
+  using C = SPC<NTH, CW, TC>;
+  constexpr int L = C::L, NPH = C::NPH;
+  __shared__ TC sY[C::NE];
+  // blocks b and b + 8 run on the same XCD; they take tiles 2P and 2P + 1, whose
+  // column runs share 128-byte lines when R = 8
+  const int b = int(blockIdx.x);
+  const int tile = (b >> 4) * 16 + ((b & 7) << 1) + ((b >> 3) & 1);
+  if (tile >= ntiles) return;
+  const int tpp = d.plane / CW;
+  const int ej = tile / tpp, tl = tile - ej * tpp;
+  const int j = ej % d.n_r;
+  const int hP = d.n_Ph >> 1;
+  const int R = min(CW / 2, hP);
+  int cbase;
+  if (R == hP) {
+    cbase = tl * CW;
+  } else {
+    const int tpr = hP / R;
+    cbase = (tl / tpr) * d.n_Ph + (tl % tpr) * R;
+  }
+  auto colc = [&](int col) { return cbase + (col & (R - 1)) + ((col & R) ? hP : 0) + (col / (2 * R)) * d.n_Ph; };
+  const int64_t slab = int64_t(ej) * d.M;
+  const int plane = d.plane;
+  const int tid = int(threadIdx.x);
+
+  {  // stage the tile: element e = combo * CW + col, combo = theta * n_phi + phi
+    const int col = tid % CW;
+    const int c = colc(col);
+    TC s_in = TC(in_scale);
+    if (mask_in && is_inflow(d, t, j, c / d.n_Ph)) s_in = TC(0);
+    TI v[C::EPT];
+#pragma unroll
+    for (int i = 0; i < C::EPT; ++i) {
+      const int e = tid + i * C::NTHR;
+      v[i] = e < C::NE ? Y[slab + int64_t(e / CW) * plane + c] : TI(0);
+    }
+#pragma unroll
+    for (int i = 0; i < C::EPT; ++i) {
+      const int e = tid + i * C::NTHR;
+      if (e < C::NE) sY[e] = TC(v[i]) * s_in;
+    }
+  }
+  __syncthreads();
+
+  const bool isPhi = tid < C::NL;
+  const bool active = tid < 2 * C::NL;
+  const int u = isPhi ? tid : tid - C::NL;
+  const int col = u % CW, w = u / CW;  // phi thread: w = theta row; theta thread: w = phi index < n_phi / 2
+  const int colp = col ^ R;
+  const int c = colc(col);
+  const int iTh = c / d.n_Ph, m = c % d.n_Ph;
+  const TC* tab = line_tab<L, TC>(LT_DERIV_T);
+  TC z[L];
+  if (active) {
+    if (isPhi) {
+      const TC s = TC(coef_sign * t.sin_Th[iTh] * t.sin_Ph[m] * t.inv_r[j] * t.inv_sin_th[w]);
+      eo_pairs_stream2<L, L / 2, true, TC>(
+          tab, 0, [&](int k) { return sY[(w * NPH + k) * CW + col]; },
+          [&](int k) { return sY[(w * NPH + L - 1 - k) * CW + col]; }, [&](int k, TC zz) { z[k] = s * zz; });
+    } else {
+      // element q < n_theta: (theta_q, phi_w, c); element L - 1 - q: (theta_q,
+      // phi_w + pi, c').  The partner coefficient is -s and the partner
+      // derivative -z, so both halves take s z.
+      const TC s = TC(coef_sign * t.sin_Th[iTh] * t.cos_Ph[m] * t.inv_r[j]);
+      eo_pairs_stream2<L, L / 2, true, TC>(
+          tab, 0, [&](int q) { return sY[(q * NPH + w) * CW + col]; },
+          [&](int q) { return sY[(q * NPH + w + NTH) * CW + colp]; }, [&](int q, TC zz) { z[q] = s * zz; });
+    }
+  }
+  __syncthreads();
+  if (active && !isPhi) {
+#pragma unroll
+    for (int q = 0; q < NTH; ++q) {
+      sY[(q * NPH + w) * CW + col] = z[q];
+      sY[(q * NPH + w + NTH) * CW + colp] = z[L - 1 - q];
+    }
+  }
+  __syncthreads();
+  if (isPhi) {
+    const int64_t o = slab + int64_t(w) * NPH * plane + c;
+#pragma unroll
+    for (int k = 0; k < NPH; ++k) T[o + int64_t(k) * plane] = z[k] + sY[(w * NPH + k) * CW + col];
+  }
+}
+
 unsigned grid_for(int64_t threads) { return unsigned((threads + CB - 1) / CB); }
 
 template <int L, typename TI, typename TO>
@@ -330,6 +449,35 @@ void launch_radial_t(const KDims& d, const KTab& t, const double* Y, double* T, 
   k_radial<KS, ACCUM><<<unsigned(blocks), CB, 0, s>>>(d, t, Y, T, transpose, mask_in, in_scale);
 }
 
+int sphere_cw(const KDims& d, bool mixed) {
+  if (d.n_ph != 2 * d.n_th || d.n_th > 16) return 0;
+  const int cw = mixed ? 32 : 16;
+  return d.plane < cw ? d.plane : cw;
+}
+
+template <int NTH, int CW, typename TI, typename TC>
+hipError_t launch_sphere_t(const KDims& d, const KTab& t, const void* Y, void* T, double coef_sign, bool mask_in,
+                           double in_scale, hipStream_t s) {
+  const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
+  const int64_t nb = (ntiles + 15) / 16 * 16;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  k_sphere<NTH, CW, TI, TC><<<unsigned(nb), SPC<NTH, CW, TC>::NTHR, 0, s>>>(
+      d, t, static_cast<const TI*>(Y), static_cast<TC*>(T), coef_sign, mask_in, in_scale, int(ntiles));
+  return hipGetLastError();
+}
+
+template <int CW, typename TI, typename TC>
+hipError_t launch_sphere_n(const KDims& d, const KTab& t, const void* Y, void* T, double coef_sign, bool mask_in,
+                           double in_scale, hipStream_t s) {
+  switch (d.n_th) {
+#define CASE(N) \
+  case N: return launch_sphere_t<N, CW, TI, TC>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
+    CASE(2) CASE(4) CASE(8) CASE(16)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
@@ -352,6 +500,30 @@ hipError_t launch_theta_mixed(const KDims& d, const KTab& t, const void* Y, bool
                               hipStream_t s) {
   return y_f32 ? launch_theta_p<float, float>(d, t, Y, T, accum, 1.0, false, 1.0, s)
                : launch_theta_p<double, float>(d, t, Y, T, accum, 1.0, false, 1.0, s);
+}
+
+bool sphere_fusable(const KDims& d, bool mixed) { return sphere_cw(d, mixed) > 0; }
+
+hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
+                         bool mask_in, double in_scale, hipStream_t s) {
+  switch (sphere_cw(d, false)) {
+    case 8: return launch_sphere_n<8, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
+    case 16: return launch_sphere_n<16, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_sphere_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T,
+                               hipStream_t s) {
+  switch (sphere_cw(d, true)) {
+    case 8:
+      return y_f32 ? launch_sphere_n<8, float, float>(d, t, Y, T, 1.0, false, 1.0, s)
+                   : launch_sphere_n<8, double, float>(d, t, Y, T, 1.0, false, 1.0, s);
+    case 32:
+      return y_f32 ? launch_sphere_n<32, float, float>(d, t, Y, T, 1.0, false, 1.0, s)
+                   : launch_sphere_n<32, double, float>(d, t, Y, T, 1.0, false, 1.0, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,

@@ -60,11 +60,12 @@ constexpr int LINE_TAB_KINDS = 4;
 enum { LT_DERIV = 0, LT_FILTER = 1, LT_DERIV_T = 2, LT_FILTER_T = 3 };
 
 // Output pairs i0 .. i0 + NPAIR - 1 of a centro-(anti)symmetric L x L matrix
-// applied to a line that is read element by element through ld(q) (from LDS):
-// the line is streamed once (e_j, o_j formed on the fly) and only the 2 NPAIR
-// accumulators stay live.  tabT is the transposed even/odd table.
-template <int L, int NPAIR, bool ANTI, typename T, typename TT, typename Load, typename Emit>
-SP6_DEV void eo_pairs_stream(const TT* __restrict__ tabT, int i0, Load&& ld, Emit&& emit) {
+// applied to a line that is read element by element (from LDS): ldA(j) returns
+// element j and ldB(j) element L - 1 - j of the line, j < L / 2.  The line is
+// streamed once (e_j, o_j formed on the fly) and only the 2 NPAIR accumulators
+// stay live.  tabT is the transposed even/odd table.
+template <int L, int NPAIR, bool ANTI, typename T, typename TT, typename LoadA, typename LoadB, typename Emit>
+SP6_DEV void eo_pairs_stream2(const TT* __restrict__ tabT, int i0, LoadA&& ldA, LoadB&& ldB, Emit&& emit) {
   constexpr int h = L / 2;
   T p[NPAIR], q[NPAIR];
 #pragma unroll
@@ -72,7 +73,7 @@ SP6_DEV void eo_pairs_stream(const TT* __restrict__ tabT, int i0, Load&& ld, Emi
   // partial unrolling bounds the number of line elements the compiler hoists
 #pragma unroll 4
   for (int j = 0; j < h; ++j) {
-    const T a = ld(j), b = ld(L - 1 - j);
+    const T a = ldA(j), b = ldB(j);
     const T e = a + b, o = a - b;
     const TT* __restrict__ At = tabT + j * h + i0;
     const TT* __restrict__ Bt = tabT + h * h + j * h + i0;
@@ -87,6 +88,13 @@ SP6_DEV void eo_pairs_stream(const TT* __restrict__ tabT, int i0, Load&& ld, Emi
     emit(i0 + ii, p[ii] + q[ii]);
     emit(L - 1 - (i0 + ii), ANTI ? (q[ii] - p[ii]) : (p[ii] - q[ii]));
   }
+}
+
+// the same with one loader ld(q) for every element q of the line
+template <int L, int NPAIR, bool ANTI, typename T, typename TT, typename Load, typename Emit>
+SP6_DEV void eo_pairs_stream(const TT* __restrict__ tabT, int i0, Load&& ld, Emit&& emit) {
+  eo_pairs_stream2<L, NPAIR, ANTI, T>(
+      tabT, i0, [&](int j) { return ld(j); }, [&](int j) { return ld(L - 1 - j); }, emit);
 }
 
 // inflow node test (Sect. 4.2): r_in with cos(Theta) > 0, r_out with cos(Theta) < 0

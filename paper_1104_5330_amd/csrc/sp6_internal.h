@@ -63,7 +63,8 @@ struct HostTables {
 };
 
 void build_host_tables(const sp6_desc& d, HostTables& t);
-// [2][2728]: derivative then filter tables of every supported line length
+// [4][2728]: derivative, filter, and the transposes of both, for every supported
+// line length (even/odd form)
 std::vector<double> build_line_tables();
 // copy the line tables into the constant memory of each kernel file (current device)
 hipError_t init_line_tables_columns(const double* tab);
@@ -99,6 +100,13 @@ hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T,
                       double coef_sign, bool mask_in, double in_scale, hipStream_t s);
 hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
                         double coef_sign, bool mask_in, double in_scale, hipStream_t s);
+// theta and phi terms together into T (not accumulated), for n_phi = 2 n_theta,
+// n_theta <= 16; the separate passes take every other shape
+bool sphere_fusable(const KDims& d, bool mixed);
+hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
+                         bool mask_in, double in_scale, hipStream_t s);
+hipError_t launch_sphere_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T,
+                               hipStream_t s);
 hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
                          bool transpose, bool mask_in, double in_scale, hipStream_t s);
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a,

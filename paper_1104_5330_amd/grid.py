@@ -148,12 +148,12 @@ class Sp6Grid:
         self._call(self.lib.sp6_step, _ptr(F, "F", self.shape), ctypes.c_double(dt), ctypes.c_int32(nsteps))
         return F
 
-    KERNEL_CLASSES = ("phi", "theta", "radial", "plane", "filter")
+    KERNEL_CLASSES = ("phi", "theta", "radial", "plane", "filter", "thetaphi")
 
     def step_timed(self, F, dt, nsteps=1):
         """step() with per-kernel HIP-event timing; returns {class: (ms_total, launches)}."""
-        ms = (ctypes.c_double * 5)()
-        n = (ctypes.c_int64 * 5)()
+        ms = (ctypes.c_double * len(self.KERNEL_CLASSES))()
+        n = (ctypes.c_int64 * len(self.KERNEL_CLASSES))()
         self._call(self.lib.sp6_step_timed, _ptr(F, "F", self.shape), ctypes.c_double(dt), ctypes.c_int32(nsteps),
                    ms, n)
         return {c: (ms[i], n[i]) for i, c in enumerate(self.KERNEL_CLASSES)}

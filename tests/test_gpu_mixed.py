@@ -36,7 +36,8 @@ def make(cfg, **kw):
     small(3, n_eps=2, n_r=9, n_theta=4, n_phi=8, n_Theta=4, n_Phi=8),
     small(3, n_eps=1, n_r=33),
     small(3, n_eps=1, n_r=65, n_theta=4, n_phi=8, n_Theta=4, n_Phi=8),
-], ids=["tiny", "small", "w3_r33", "r65"])
+    small(3, n_eps=1, n_r=5, n_theta=4, n_phi=8, n_Theta=32, n_Phi=64),
+], ids=["tiny", "small", "w3_r33", "r65", "wide_plane"])
 def test_mixed_terms_and_rhs(cfg):
     G = make(cfg)
     F = synth.fields.shell_state(cfg)

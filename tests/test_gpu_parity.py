@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 # (name, config) shapes: tiny, ragged (odd n_eps * n_r with the 16-plane kernel),
-# the small workload, a reduced workload-2 shape, one of each line length
+# the small workload, a reduced workload-2 shape, one of each line length, and a
+# wide (Theta, Phi) plane whose fused theta-phi tiles are split Theta rows
 SHAPES = {
     "tiny": small(3, n_eps=1, n_r=5, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
     "ragged": small(3, n_eps=3, n_r=7, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
@@ -23,6 +24,7 @@ SHAPES = {
     "w2_reduced": small(3, n_eps=2, n_r=9),
     "mixed_lines": small(3, n_eps=2, n_r=17, n_theta=4, n_phi=64, n_Theta=8, n_Phi=16),
     "big_lines": small(3, n_eps=1, n_r=6, n_theta=32, n_phi=8, n_Theta=32, n_Phi=64),
+    "wide_plane": small(3, n_eps=2, n_r=5, n_theta=4, n_phi=8, n_Theta=32, n_Phi=64),
 }
 SHAPES["cfg1"] = synth.config(1).scaled(physics="scatter")
 
@@ -83,7 +85,7 @@ def test_rhs_switches(bc, scat):
     assert maxrel(got, ops.rhs(F, g, k, s, e, bc=bc, scattering=scat)) <= TOL
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "big_lines"])
+@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "big_lines", "wide_plane"])
 def test_step(name):
     cfg = SHAPES[name]
     banner(f"step {name}")
@@ -107,7 +109,7 @@ def test_step_is_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced"])
+@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "wide_plane"])
 def test_adjoint_step(name):
     cfg = SHAPES[name]
     banner(f"adjoint {name}")
