@@ -148,7 +148,7 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
   constexpr int NRT = (KS + 3) / 4;
   constexpr int NWV = CB / 64;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = wave_uniform(threadIdx.x >> 6);
   const int lr = lane & 15, lk = lane >> 4;
   const double* __restrict__ Dp = transpose ? t.DpadT : t.Dpad;
   double a[NRT][KS];
@@ -158,33 +158,25 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
     for (int s = 0; s < KS; ++s) a[rt][s] = Dp[(16 * rt + lr) * t.KP + 4 * s + lk];
 
   // column groups of 16; each workgroup walks one contiguous range of them, its
-  // wavefronts side by side (all sizes fit in 32 bits)
+  // wavefronts side by side.  Addresses are split into a wave-uniform part (group
+  // base and row block) and a 32-bit per-lane part lk M + lr, which keeps the
+  // per-lane address registers to one.
   const int gpe = int(d.M / 16);
   const int ngroups = gpe * d.n_eps;
   const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
   const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
   const int64_t M = d.M;
+  const uint32_t off = uint32_t(lk) * uint32_t(M) + uint32_t(lr);
   for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
     const int e = g / gpe;
-    const int col = (g - e * gpe) * 16 + lr;
-    const int64_t eb = int64_t(e) * d.n_r * M + col;
-    const int iTh = (col / d.n_Ph) % d.n_Th;
+    const int c0 = (g - e * gpe) * 16;
+    const int64_t gb = int64_t(e) * d.n_r * M + c0;
+    const double* __restrict__ Yg = Y + gb;
+    double* __restrict__ Tg = T + gb;
+    const int iTh = ((c0 + lr) / d.n_Ph) % d.n_Th;
     double b[KS];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int row = 4 * s + lk;
-      b[s] = row < d.n_r ? Y[eb + row * M] : 0.0;
-    }
-    double tv[ACCUM ? NRT * 4 : 1];
-    if constexpr (ACCUM) {
-#pragma unroll
-      for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * rt + lk + 4 * v;
-          tv[rt * 4 + v] = row < d.n_r ? T[eb + row * M] : 0.0;
-        }
-    }
+    for (int s = 0; s < KS; ++s) b[s] = 4 * s + lk < d.n_r ? Yg[int64_t(4 * s) * M + off] : 0.0;
     if (mask_in) {
 #pragma unroll
       for (int s = 0; s < KS; ++s)
@@ -201,18 +193,27 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
 #pragma unroll
       for (int s = 0; s < KS; ++s) acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][s], b[s], acc[rt], 0, 0, 0);
     }
+    // T is requested after the products, which keeps it out of the register peak
+    double tv[ACCUM ? NRT * 4 : 1];
+    if constexpr (ACCUM) {
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          tv[rt * 4 + v] = 16 * rt + lk + 4 * v < d.n_r ? Tg[int64_t(16 * rt + 4 * v) * M + off] : 0.0;
+    }
     const double cT = t.cos_Th[iTh];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * rt + lk + 4 * v;
-        if (row < d.n_r) {
+        if (16 * rt + lk + 4 * v < d.n_r) {
           const double val = cT * acc[rt][v];
+          double* dst = Tg + int64_t(16 * rt + 4 * v) * M + off;
           if constexpr (ACCUM)
-            T[eb + row * M] = tv[rt * 4 + v] + val;
+            *dst = tv[rt * 4 + v] + val;
           else
-            T[eb + row * M] = val;
+            *dst = val;
         }
       }
   }
@@ -442,9 +443,12 @@ template <int KS, bool ACCUM>
 void launch_radial_t(const KDims& d, const KTab& t, const double* Y, double* T, bool transpose, bool mask_in,
                      double in_scale, hipStream_t s) {
   const int64_t ngroups = (d.M / 16) * d.n_eps;
-  // a few resident waves of workgroups per compute unit
+  // one resident round of workgroups: every workgroup walks an equal contiguous range
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_radial<KS, ACCUM>, CB, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
   int64_t blocks = (ngroups + 3) / 4;
-  const int64_t cap = int64_t(d.ncu) * 8;
+  const int64_t cap = int64_t(d.ncu) * per_cu;
   if (blocks > cap) blocks = cap;
   k_radial<KS, ACCUM><<<unsigned(blocks), CB, 0, s>>>(d, t, Y, T, transpose, mask_in, in_scale);
 }

@@ -31,7 +31,7 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
                                                       float* __restrict__ T) {
   constexpr int KS = (NRT + 1) / 2;
   constexpr int NWV = CB / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = wave_uniform(threadIdx.x >> 6);
   const int lr = lane & 15, lg = lane >> 4;
   // A operands: three bf16 planes of the padded matrix, 8 consecutive k per lane
   v8bf A[3][NRT][KS];
@@ -50,33 +50,28 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
   const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
   const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
   const int64_t M = d.M;
+  // wave-uniform group base plus 32-bit per-lane offsets (B rows 8 lg + q, C rows 4 lg + v)
+  const uint32_t offB = uint32_t(8 * lg) * uint32_t(M) + uint32_t(lr);
+  const uint32_t offC = uint32_t(4 * lg) * uint32_t(M) + uint32_t(lr);
   for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
     const int e = g / gpe;
-    const int col = (g - e * gpe) * 16 + lr;
-    const int64_t eb = int64_t(e) * d.n_r * M + col;
+    const int c0 = (g - e * gpe) * 16;
+    const int64_t gb = int64_t(e) * d.n_r * M + c0;
+    const TI* __restrict__ Yg = Y + gb;
+    float* __restrict__ Tg = T + gb;
     v8bf B[3][KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int row = 32 * s + 8 * lg + q;
-        const float y = row < d.n_r ? float(Y[eb + row * M]) : 0.0f;
+        const float y = row < d.n_r ? float(Yg[int64_t(32 * s + q) * M + offB]) : 0.0f;
         __bf16 b1, b2, b3;
         split3(y, b1, b2, b3);
         B[0][s][q] = b1;
         B[1][s][q] = b2;
         B[2][s][q] = b3;
       }
-    float tv[ACCUM ? NRT * 4 : 1];
-    if constexpr (ACCUM) {
-#pragma unroll
-      for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * rt + 4 * lg + v;
-          tv[rt * 4 + v] = row < d.n_r ? T[eb + row * M] : 0.0f;
-        }
-    }
     v4f acc[NRT];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt) {
@@ -92,7 +87,18 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
         acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0][rt][s], B[0][s], acc[rt], 0, 0, 0);
       }
     }
-    const float cT = float(t.cos_Th[(col / d.n_Ph) % d.n_Th]);
+    // T is requested after the products, which keeps it out of the register peak
+    float tv[ACCUM ? NRT * 4 : 1];
+    if constexpr (ACCUM) {
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * rt + 4 * lg + v;
+          tv[rt * 4 + v] = row < d.n_r ? Tg[int64_t(16 * rt + v) * M + offC] : 0.0f;
+        }
+    }
+    const float cT = float(t.cos_Th[((c0 + lr) / d.n_Ph) % d.n_Th]);
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
@@ -100,10 +106,11 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
         const int row = 16 * rt + 4 * lg + v;
         if (row < d.n_r) {
           const float val = cT * acc[rt][v];
+          float* dst = Tg + int64_t(16 * rt + v) * M + offC;
           if constexpr (ACCUM)
-            T[eb + row * M] = tv[rt * 4 + v] + val;
+            *dst = tv[rt * 4 + v] + val;
           else
-            T[eb + row * M] = val;
+            *dst = val;
         }
       }
   }
@@ -112,14 +119,18 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
 template <int NRT, typename TI>
 void launch_t(const KDims& d, const KTab& t, const void* Y, float* T, bool accum, hipStream_t s) {
   const int64_t ngroups = (d.M / 16) * d.n_eps;
-  int64_t blocks = (ngroups + 3) / 4;
-  const int64_t cap = int64_t(d.ncu) * 8;
-  if (blocks > cap) blocks = cap;
+  // one resident round of workgroups: every workgroup walks an equal contiguous range
+  auto blocks_for = [&](auto kernel) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, CB, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int64_t blocks = (ngroups + 3) / 4, cap = int64_t(d.ncu) * per_cu;
+    return unsigned(blocks < cap ? blocks : cap);
+  };
   const TI* y = static_cast<const TI*>(Y);
   if (accum)
-    k_radial_bf16x3<NRT, true, TI><<<unsigned(blocks), CB, 0, s>>>(d, t, y, T);
+    k_radial_bf16x3<NRT, true, TI><<<blocks_for(k_radial_bf16x3<NRT, true, TI>), CB, 0, s>>>(d, t, y, T);
   else
-    k_radial_bf16x3<NRT, false, TI><<<unsigned(blocks), CB, 0, s>>>(d, t, y, T);
+    k_radial_bf16x3<NRT, false, TI><<<blocks_for(k_radial_bf16x3<NRT, false, TI>), CB, 0, s>>>(d, t, y, T);
 }
 
 template <typename TI>
