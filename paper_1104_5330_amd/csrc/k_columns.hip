@@ -158,25 +158,53 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
     for (int s = 0; s < KS; ++s) a[rt][s] = Dp[(16 * rt + lr) * t.KP + 4 * s + lk];
 
   // column groups of 16; each workgroup walks one contiguous range of them, its
-  // wavefronts side by side.  Addresses are split into a wave-uniform part (group
-  // base and row block) and a 32-bit per-lane part lk M + lr, which keeps the
-  // per-lane address registers to one.
+  // wavefronts side by side.  Addresses are a wave-uniform row pointer plus the
+  // 32-bit per-lane byte offset of row lk, column lr.  Only the last k-step and
+  // the last row tile can reach past n_r (KS = ceil(n_r / 4)); every other load
+  // and store is unconditional.
   const int gpe = int(d.M / 16);
   const int ngroups = gpe * d.n_eps;
   const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
   const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
   const int64_t M = d.M;
-  const uint32_t off = uint32_t(lk) * uint32_t(M) + uint32_t(lr);
+  const int n_r = d.n_r;
+  const uint32_t boff = (uint32_t(lk) * uint32_t(M) + uint32_t(lr)) * 8u;
+  auto ld = [&](const double* row) {
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(row) + boff);
+  };
+  auto at = [&](double* row) { return reinterpret_cast<double*>(reinterpret_cast<char*>(row) + boff); };
+  // every extent is a power of two: divisions become shifts
+  const int sh_g = __builtin_ctz(gpe), sh_P = __builtin_ctz(d.n_Ph);
   for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
-    const int e = g / gpe;
-    const int c0 = (g - e * gpe) * 16;
-    const int64_t gb = int64_t(e) * d.n_r * M + c0;
+    const int e = g >> sh_g;
+    const int c0 = (g & (gpe - 1)) * 16;
+    const int64_t gb = int64_t(e) * n_r * M + c0;
     const double* __restrict__ Yg = Y + gb;
     double* __restrict__ Tg = T + gb;
-    const int iTh = ((c0 + lr) / d.n_Ph) % d.n_Th;
+    const int iTh = ((c0 + lr) >> sh_P) & (d.n_Th - 1);
+    const double cT = t.cos_Th[iTh];
     double b[KS];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) b[s] = 4 * s + lk < d.n_r ? Yg[int64_t(4 * s) * M + off] : 0.0;
+    for (int s = 0; s < KS; ++s) {
+      const double* row = Yg + int64_t(4 * s) * M;
+      if (s < KS - 1)
+        b[s] = ld(row);
+      else
+        b[s] = 4 * s + lk < n_r ? ld(row) : 0.0;
+    }
+    double tv[ACCUM ? NRT * 4 : 1];
+    if constexpr (ACCUM) {
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const double* row = Tg + int64_t(16 * rt + 4 * v) * M;
+          if (rt < NRT - 1)
+            tv[rt * 4 + v] = ld(row);
+          else
+            tv[rt * 4 + v] = 16 * rt + lk + 4 * v < n_r ? ld(row) : 0.0;
+        }
+    }
     if (mask_in) {
 #pragma unroll
       for (int s = 0; s < KS; ++s)
@@ -193,23 +221,13 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
 #pragma unroll
       for (int s = 0; s < KS; ++s) acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][s], b[s], acc[rt], 0, 0, 0);
     }
-    // T is requested after the products, which keeps it out of the register peak
-    double tv[ACCUM ? NRT * 4 : 1];
-    if constexpr (ACCUM) {
-#pragma unroll
-      for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          tv[rt * 4 + v] = 16 * rt + lk + 4 * v < d.n_r ? Tg[int64_t(16 * rt + 4 * v) * M + off] : 0.0;
-    }
-    const double cT = t.cos_Th[iTh];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        if (16 * rt + lk + 4 * v < d.n_r) {
+        if (rt < NRT - 1 || 16 * rt + lk + 4 * v < n_r) {
           const double val = cT * acc[rt][v];
-          double* dst = Tg + int64_t(16 * rt + 4 * v) * M + off;
+          double* dst = at(Tg + int64_t(16 * rt + 4 * v) * M);
           if constexpr (ACCUM)
             *dst = tv[rt * 4 + v] + val;
           else

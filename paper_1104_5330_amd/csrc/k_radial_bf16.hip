@@ -50,24 +50,54 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
   const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
   const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
   const int64_t M = d.M;
-  // wave-uniform group base plus 32-bit per-lane offsets (B rows 8 lg + q, C rows 4 lg + v)
-  const uint32_t offB = uint32_t(8 * lg) * uint32_t(M) + uint32_t(lr);
-  const uint32_t offC = uint32_t(4 * lg) * uint32_t(M) + uint32_t(lr);
+  const int n_r = d.n_r;
+  // wave-uniform row pointers plus 32-bit per-lane byte offsets (B rows 8 lg + q,
+  // C rows 4 lg + v).  Only the last k-step and the last row tile can reach past
+  // n_r; every other load and store is unconditional.
+  const uint32_t offB = (uint32_t(8 * lg) * uint32_t(M) + uint32_t(lr)) * uint32_t(sizeof(TI));
+  const uint32_t offC = (uint32_t(4 * lg) * uint32_t(M) + uint32_t(lr)) * 4u;
+  auto ldY = [&](const TI* row) { return *reinterpret_cast<const TI*>(reinterpret_cast<const char*>(row) + offB); };
+  auto atT = [&](float* row) { return reinterpret_cast<float*>(reinterpret_cast<char*>(row) + offC); };
+  // every extent is a power of two: divisions become shifts
+  const int sh_g = __builtin_ctz(gpe), sh_P = __builtin_ctz(d.n_Ph);
   for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
-    const int e = g / gpe;
-    const int c0 = (g - e * gpe) * 16;
-    const int64_t gb = int64_t(e) * d.n_r * M + c0;
+    const int e = g >> sh_g;
+    const int c0 = (g & (gpe - 1)) * 16;
+    const float cT = float(t.cos_Th[((c0 + lr) >> sh_P) & (d.n_Th - 1)]);
+    const int64_t gb = int64_t(e) * n_r * M + c0;
     const TI* __restrict__ Yg = Y + gb;
     float* __restrict__ Tg = T + gb;
+    float y[KS][8];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const TI* row = Yg + int64_t(32 * s + q) * M;
+        if (s < KS - 1)
+          y[s][q] = float(ldY(row));
+        else
+          y[s][q] = 32 * s + 8 * lg + q < n_r ? float(ldY(row)) : 0.0f;
+      }
+    float tv[ACCUM ? NRT * 4 : 1];
+    if constexpr (ACCUM) {
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          float* row = Tg + int64_t(16 * rt + v) * M;
+          if (rt < NRT - 1)
+            tv[rt * 4 + v] = *atT(row);
+          else
+            tv[rt * 4 + v] = 16 * rt + 4 * lg + v < n_r ? *atT(row) : 0.0f;
+        }
+    }
     v8bf B[3][KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int row = 32 * s + 8 * lg + q;
-        const float y = row < d.n_r ? float(Yg[int64_t(32 * s + q) * M + offB]) : 0.0f;
         __bf16 b1, b2, b3;
-        split3(y, b1, b2, b3);
+        split3(y[s][q], b1, b2, b3);
         B[0][s][q] = b1;
         B[1][s][q] = b2;
         B[2][s][q] = b3;
@@ -87,26 +117,13 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
         acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[0][rt][s], B[0][s], acc[rt], 0, 0, 0);
       }
     }
-    // T is requested after the products, which keeps it out of the register peak
-    float tv[ACCUM ? NRT * 4 : 1];
-    if constexpr (ACCUM) {
-#pragma unroll
-      for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = 16 * rt + 4 * lg + v;
-          tv[rt * 4 + v] = row < d.n_r ? Tg[int64_t(16 * rt + v) * M + offC] : 0.0f;
-        }
-    }
-    const float cT = float(t.cos_Th[((c0 + lr) / d.n_Ph) % d.n_Th]);
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = 16 * rt + 4 * lg + v;
-        if (row < d.n_r) {
+        if (rt < NRT - 1 || 16 * rt + 4 * lg + v < n_r) {
           const float val = cT * acc[rt][v];
-          float* dst = Tg + int64_t(16 * rt + v) * M + offC;
+          float* dst = atT(Tg + int64_t(16 * rt + v) * M);
           if constexpr (ACCUM)
             *dst = tv[rt * 4 + v] + val;
           else
