@@ -64,14 +64,16 @@ enum { LT_DERIV = 0, LT_FILTER = 1, LT_DERIV_T = 2, LT_FILTER_T = 3 };
 // element j and ldB(j) element L - 1 - j of the line, j < L / 2.  The line is
 // streamed once (e_j, o_j formed on the fly) and only the 2 NPAIR accumulators
 // stay live.  tabT is the transposed even/odd table.
-template <int L, int NPAIR, bool ANTI, typename T, typename TT, typename LoadA, typename LoadB, typename Emit>
+template <int L, int NPAIR, bool ANTI, typename T, int U = 4, typename TT, typename LoadA, typename LoadB,
+          typename Emit>
 SP6_DEV void eo_pairs_stream2(const TT* __restrict__ tabT, int i0, LoadA&& ldA, LoadB&& ldB, Emit&& emit) {
   constexpr int h = L / 2;
   T p[NPAIR], q[NPAIR];
 #pragma unroll
   for (int ii = 0; ii < NPAIR; ++ii) p[ii] = q[ii] = T(0);
-  // partial unrolling bounds the number of line elements the compiler hoists
-#pragma unroll 4
+  // partial unrolling (U) bounds the number of line elements and table entries
+  // the compiler hoists into registers
+#pragma unroll U
   for (int j = 0; j < h; ++j) {
     const T a = ldA(j), b = ldB(j);
     const T e = a + b, o = a - b;
@@ -91,9 +93,9 @@ SP6_DEV void eo_pairs_stream2(const TT* __restrict__ tabT, int i0, LoadA&& ldA, 
 }
 
 // the same with one loader ld(q) for every element q of the line
-template <int L, int NPAIR, bool ANTI, typename T, typename TT, typename Load, typename Emit>
+template <int L, int NPAIR, bool ANTI, typename T, int U = 4, typename TT, typename Load, typename Emit>
 SP6_DEV void eo_pairs_stream(const TT* __restrict__ tabT, int i0, Load&& ld, Emit&& emit) {
-  eo_pairs_stream2<L, NPAIR, ANTI, T>(
+  eo_pairs_stream2<L, NPAIR, ANTI, T, U>(
       tabT, i0, [&](int j) { return ld(j); }, [&](int j) { return ld(L - 1 - j); }, emit);
 }
 

@@ -142,56 +142,72 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
   TO* ynext = static_cast<TO*>(a.ynext);
 
   // each workgroup walks one contiguous range of plane groups; every global
-  // operand of the next group is loaded one iteration ahead (register double
-  // buffering), so its loads are in flight during the lines and the epilogue
+  // operand of the next group (state, T, acc, y, and the per-plane coefficients)
+  // is loaded one iteration ahead (register double buffering), so its loads are
+  // in flight during the lines and the epilogue.  Groups that lie wholly inside
+  // the array (all but possibly the last) load without per-lane predicates.
   const int per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
   const int gbeg = per_blk * blockIdx.x, gend = min(ngroups, gbeg + per_blk);
-  auto load_y = [&](int g, TY* yi) {
+  const bool apply = a.mode == PM_APPLY, scat = !apply && d.scattering;
+  const int sh_ph = __builtin_ctz(d.n_ph), sh_th = __builtin_ctz(d.n_th);
+  auto load_group = [&](int g, TY* yi, TO* ti, double* ai, double* yo) {
     const int plane0 = g * C::NPW;
+    const int64_t base = int64_t(plane0) * C::PLANE;
+    const TY* __restrict__ Yb = Yin + base;
+    const TO* __restrict__ Tb = Tin + base;
+    const double* __restrict__ Ab = a.accsrc + base;
+    const double* __restrict__ Xb = a.ysrc + base;
+    if (plane0 + C::NPW <= npl) {
 #pragma unroll
-    for (int q = 0; q < C::PPT; ++q) {
-      const int p = tid + q * C::NTHR;
-      const bool ok = g < gend && plane0 + p / C::PLANE < npl;
-      yi[q] = ok ? Yin[int64_t(plane0) * C::PLANE + p] : TY(0);
+      for (int q = 0; q < C::PPT; ++q) {
+        const uint32_t p = uint32_t(tid + q * C::NTHR);
+        yi[q] = Yb[p];
+        ti[q] = needT ? Tb[p] : TO(0);
+        if constexpr (NA) ai[q] = Ab[p];
+        if constexpr (NY) yo[q] = Xb[p];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < C::PPT; ++q) {
+        const uint32_t p = uint32_t(tid + q * C::NTHR);
+        const bool ok = plane0 + int(p) / C::PLANE < npl;
+        yi[q] = ok ? Yb[p] : TY(0);
+        ti[q] = (ok && needT) ? Tb[p] : TO(0);
+        if constexpr (NA) ai[q] = ok ? Ab[p] : 0.0;
+        if constexpr (NY) yo[q] = ok ? Xb[p] : 0.0;
+      }
     }
   };
-  auto load_rest = [&](int g, TO* ti, double* ai, double* yo) {
-    const int plane0 = g * C::NPW;
-#pragma unroll
-    for (int q = 0; q < C::PPT; ++q) {
-      const int p = tid + q * C::NTHR;
-      const bool ok = g < gend && plane0 + p / C::PLANE < npl;
-      const int64_t gp = int64_t(plane0) * C::PLANE + p;
-      ti[q] = (ok && needT) ? Tin[gp] : TO(0);
-      if constexpr (NA) ai[q] = ok ? a.accsrc[gp] : 0.0;
-      if constexpr (NY) yo[q] = ok ? a.ysrc[gp] : 0.0;
+  // thread tid < NPW keeps the coefficients of plane g NPW + tid
+  auto load_info = [&](int g, PlaneInfo& pi) {
+    if (tid < C::NPW) {
+      const int pid = min(g * C::NPW + tid, npl - 1);
+      const int l = (pid >> sh_ph) & (d.n_th - 1);
+      const int j = (pid >> (sh_ph + sh_th)) % d.n_r;
+      pi.inv_r = t.inv_r[j];
+      pi.cot_th = t.cot_th[l];
+      pi.kappa = apply ? 0.0 : cf.kappa[pid];
+      pi.eta = apply ? 0.0 : cf.eta[pid];
+      pi.sigma = scat ? cf.sigma[pid] : 0.0;
+      pi.mean = 0.0;
+      pi.j = j;
+      pi.pad = 0;
     }
   };
   TY yin[C::PPT];
   TO tn[C::PPT];
   double an[NA ? C::PPT : 1], yn[NY ? C::PPT : 1];
+  PlaneInfo pin{};
   int grp = gbeg;
-  load_y(grp, yin);
-  load_rest(grp, tn, an, yn);
+  if (grp < gend) {
+    load_group(grp, yin, tn, an, yn);
+    load_info(grp, pin);
+  }
   for (; grp < gend; ++grp) {
     const int plane0 = grp * C::NPW;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) sY[C::lds(tid + q * C::NTHR)] = yin[q];
-    if (tid < C::NPW) {
-      const int pid = min(plane0 + tid, npl - 1);
-      const int l = (pid / d.n_ph) % d.n_th;
-      const int j = (pid / (d.n_ph * d.n_th)) % d.n_r;
-      PlaneInfo pi;
-      pi.inv_r = t.inv_r[j];
-      pi.cot_th = t.cot_th[l];
-      pi.kappa = a.mode == PM_APPLY ? 0.0 : cf.kappa[pid];
-      pi.eta = a.mode == PM_APPLY ? 0.0 : cf.eta[pid];
-      pi.sigma = (a.mode == PM_APPLY || !d.scattering) ? 0.0 : cf.sigma[pid];
-      pi.mean = 0.0;
-      pi.j = j;
-      pi.pad = 0;
-      sPl[tid] = pi;
-    }
+    if (tid < C::NPW) sPl[tid] = pin;
     __syncthreads();
     TO tv[C::PPT];
     double av[NA ? C::PPT : 1], yv[NY ? C::PPT : 1];
@@ -201,8 +217,10 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       if constexpr (NA) av[q] = an[q];
       if constexpr (NY) yv[q] = yn[q];
     }
-    load_y(grp + 1, yin);
-    load_rest(grp + 1, tn, an, yn);
+    if (grp + 1 < gend) {
+      load_group(grp + 1, yin, tn, an, yn);
+      load_info(grp + 1, pin);
+    }
 
     {  // line phase
       const int lane = tid & 63;
@@ -211,7 +229,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       const bool isTh = li < NT;
       const LineMap<NT> lm = line_map<NT>(pl, li);
       const double inv_r = sPl[pl].inv_r, cot_th = sPl[pl].cot_th;
-      if (d.scattering && a.mode != PM_APPLY && part == 0) {
+      if (scat && part == 0) {
         // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
         double s = 0.0;
         if (!isTh) {
@@ -226,18 +244,19 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       TC* out = sR[isTh ? 0 : 1];
       // the line is streamed from LDS against the transposed table instead of
       // being held in registers: fewer registers, higher occupancy
-      eo_pairs_stream<C::L, C::PPW, true, TC>(
+      eo_pairs_stream<C::L, C::PPW, true, TC, 2>(
           line_tab<C::L, TC>(LT_DERIV_T), part * C::PPW, [&](int q) { return TC(sY[lm.idx(q)]); },
           [&](int q, TC z) { out[lm.idx(q)] = TC(line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh)) * z; });
     }
     __syncthreads();
 
+    const int64_t base = int64_t(plane0) * C::PLANE;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int p = tid + q * C::NTHR;
       const int pl = p / C::PLANE;
       if (plane0 + pl >= npl) continue;
-      const int64_t gp = int64_t(plane0) * C::PLANE + p;
+      const int64_t gp = base + uint32_t(p);
       const int lp = C::lds(p);
       double LY = double(tv[q]);
       if (useTh) LY += double(sR[0][lp]);
