@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The right-hand side is affine in F: rhs(Y) = A Y + M eta with
-A = M (-L - (kappa + sigma) I + sigma avg), M the inflow mask and avg the
-broadcast angular mean.  For y1 = y + dt/6 (k1 + 2 k2 + 2 k3 + k4) with
+A = M (-L - (kappa + sigma) I + sigma K), M the inflow mask and K the
+in-scattering operator (the broadcast angular mean for isotropic scattering).  For y1 = y + dt/6 (k1 + 2 k2 + 2 k3 + k4) with
 k_s = rhs(Y_s), the exact transpose of the step is (lam = dLoss/dy1):
 
     kb4 = dt/6 lam
@@ -35,7 +35,7 @@ def adjoint_step(y, lam, g, p, dt):
     (Y1, Y2, Y3, Y4), _ = step.rk4_stages(y, g, p, dt)
 
     def AT(x):
-        return ops.rhs_linear_T(x, g, p.kappa, p.sigma, bc=p.bc, scattering=p.scattering)
+        return ops.rhs_linear_T(x, g, p.kappa, p.sigma, bc=p.bc, scattering=p.scattering, kernel=p.kernel)
 
     kb4 = (dt / 6.0) * lam
     a4 = AT(kb4)
@@ -56,7 +56,7 @@ def adjoint_step(y, lam, g, p, dt):
         gk -= np.sum(mk * Ys, axis=(4, 5))
         ge += np.sum(mk, axis=(4, 5))
         if p.scattering:
-            gs += np.sum(mk * (ops.angular_mean(Ys, g) - Ys), axis=(4, 5))
+            gs += np.sum(mk * (ops.scatter_in(Ys, g, p.kernel) - Ys), axis=(4, 5))
     return lam_prev, gk, ge, gs
 
 

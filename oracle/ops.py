@@ -17,11 +17,23 @@ Readings of the paper used here (each is listed in the design notes):
   from Eqs. omegax-omegaz).  Nodes are half-shifted, so no node sits on a pole
   or on Theta = pi/2.
 * The collision term is Eq. (Transp) with coherent scattering
-  (Eq. sigmadif), the isotropic kernel (Eq. sigman with B = 0), the density
-  absorbed into kappa = n sigma_a, sigma = n A, eta = n S, and without the
-  induced-process factors (they make the equation nonlinear):
-      C(F) = eta - (kappa + sigma) F + sigma <F>,
-      <F>  = (1/4pi) sum_i sum_m w_i (2pi/n_Phi) F_im   (Fejer in cos Theta).
+  (Eq. sigmadif), the density absorbed into kappa = n sigma_a, sigma = n x (total
+  scattering cross section), eta = n S, and without the induced-process factors
+  (they make the equation nonlinear):
+      C(F) = eta - (kappa + sigma) F + sigma (K F),
+      (K F)(omega) = sum_{omega'} wq(omega') p(omega . omega') F(omega'),
+      wq(Theta_i, Phi_m) = w_i (2pi/n_Phi) / (4pi)   (Fejer in cos Theta),
+  with the phase function p(mu) = c0 + c1 mu + c2 mu^2 normalised by
+  c0 = 1 - c2/3 (its mean over the sphere is one, so sigma is the total
+  scattering opacity).  Isotropic scattering (Eq. sigman with B = 0) is
+  c1 = c2 = 0, where K F is the angular mean <F>; Eq. sigman gives c1 = B/A
+  (-1/3 and -1/10 for the neutron and proton kernels, Eqs. crossnun, crossnup);
+  Thomson scattering, Eq. sigmaTh, is p = (3/4)(1 + mu^2): its printed
+  prefactor is garbled, and this normalisation is the one of the azimuthally
+  integrated kernel (3/8)(1 + cos^2 cos'^2 + sin^2 sin'^2 / 2) of App. B
+  (Eq. speccons).  Directions are omega = (cos Theta, sin Theta cos Phi,
+  sin Theta sin Phi) in the local orthonormal frame of the position; omega .
+  omega' does not depend on that frame.
 * Inflow (Sect. 4.2, Eq. Sphedif): F is imposed at r = r_in where
   cos(Theta) > 0 and at r = r_out where cos(Theta) < 0; the right-hand side is
   set to zero there (a collocation analogue of the paper's Tau imposition).
@@ -181,18 +193,62 @@ def angular_mean_T(X, g):
     return np.sum(X, axis=(AX_TTH, AX_TPH), keepdims=True) * w
 
 
+def plane_directions(g):
+    """Unit vectors omega of the (Theta, Phi) nodes in the local frame, shape
+    (n_Theta n_Phi, 3), rows in C order over (i, m)."""
+    Th, Ph = np.meshgrid(g.Theta, g.Phi, indexing="ij")
+    om = np.stack([np.cos(Th), np.sin(Th) * np.cos(Ph), np.sin(Th) * np.sin(Ph)], axis=-1)
+    return om.reshape(-1, 3)
+
+
+def scattering_matrix(g, kernel):
+    """Dense in-scattering matrix of one (Theta, Phi) plane for the phase
+    function p(mu) = c0 + c1 mu + c2 mu^2, kernel = (c1, c2), c0 = 1 - c2/3:
+    K[a, b] = wq(b) p(omega_a . omega_b), rows and columns in C order over (i, m)."""
+    c1, c2 = kernel
+    c0 = 1.0 - c2 / 3.0
+    om = plane_directions(g)
+    mu = om @ om.T
+    wq = np.repeat(g.w_Theta * (2.0 * np.pi / g.n_Phi) / (4.0 * np.pi), g.n_Phi)
+    return (c0 + c1 * mu + c2 * mu * mu) * wq[None, :]
+
+
+def is_isotropic(kernel):
+    return kernel is None or (kernel[0] == 0.0 and kernel[1] == 0.0)
+
+
+def scatter_in(F, g, kernel=None):
+    """K F over every (Theta, Phi) plane (the angular mean <F>, broadcastable,
+    for the isotropic kernel)."""
+    if is_isotropic(kernel):
+        return angular_mean(F, g)
+    K = scattering_matrix(g, kernel)
+    n = g.n_Theta * g.n_Phi
+    return (F.reshape(-1, n) @ K.T).reshape(F.shape)
+
+
+def scatter_in_T(X, g, kernel=None):
+    """Transpose of F -> K F."""
+    if is_isotropic(kernel):
+        return angular_mean_T(X, g)
+    K = scattering_matrix(g, kernel)
+    n = g.n_Theta * g.n_Phi
+    X = np.broadcast_to(X, X.shape[:4] + (g.n_Theta, g.n_Phi))
+    return (X.reshape(-1, n) @ K).reshape(X.shape)
+
+
 def expand_coeff(c, g):
     """Isotropic coefficient field [eps][r][theta][phi] -> rank-6 broadcastable."""
     c = np.asarray(c, dtype=np.float64)
     return c.reshape(g.n_eps, g.n_r, g.n_theta, g.n_phi, 1, 1)
 
 
-def collision(F, g, kappa, sigma, eta):
-    """C(F) = eta - (kappa + sigma) F + sigma <F>  (see the module docstring)."""
+def collision(F, g, kappa, sigma, eta, kernel=None):
+    """C(F) = eta - (kappa + sigma) F + sigma K F  (see the module docstring)."""
     k = expand_coeff(kappa, g)
     s = expand_coeff(sigma, g)
     e = expand_coeff(eta, g)
-    return e - (k + s) * F + s * angular_mean(F, g)
+    return e - (k + s) * F + s * scatter_in(F, g, kernel)
 
 
 def inflow_mask(g):
@@ -220,23 +276,23 @@ def project_inflow(F, g, g_in=None, g_out=None):
     return F
 
 
-def rhs(F, g, kappa, sigma, eta, bc=True, scattering=True):
+def rhs(F, g, kappa, sigma, eta, bc=True, scattering=True, kernel=None):
     """Right-hand side dF/dt = -L_sph F + C(F) (Eqs. Transpfpsph, Transp), set to
     zero at the inflow nodes when bc is True."""
     s = sigma if scattering else np.zeros_like(np.asarray(sigma, np.float64))
-    out = -apply_L(F, g) + collision(F, g, kappa, s, eta)
+    out = -apply_L(F, g) + collision(F, g, kappa, s, eta, kernel)
     if bc:
         out = out * inflow_mask(g)
     return out
 
 
-def rhs_linear_T(X, g, kappa, sigma, bc=True, scattering=True):
-    """Transpose of the linear part of rhs (A^T X, with A = M(-L - (k+s) + s avg))."""
+def rhs_linear_T(X, g, kappa, sigma, bc=True, scattering=True, kernel=None):
+    """Transpose of the linear part of rhs (A^T X, with A = M(-L - (k+s) + s K))."""
     if bc:
         X = X * inflow_mask(g)
     k = expand_coeff(kappa, g)
     s = expand_coeff(sigma, g) if scattering else 0.0 * k
-    return -apply_LT(X, g) - (k + s) * X + angular_mean_T(s * X, g)
+    return -apply_LT(X, g) - (k + s) * X + scatter_in_T(s * X, g, kernel)
 
 
 # ---------------------------------------------------------------------------
@@ -275,7 +331,7 @@ def apply_filter(F, g):
 # single-point evaluation (for sampled checks of large grids)
 
 
-def rhs_at(F, g, kappa, sigma, eta, idx, bc=True, scattering=True):
+def rhs_at(F, g, kappa, sigma, eta, idx, bc=True, scattering=True, kernel=None):
     """The right-hand side at a single node idx = (e, j, l, k, i, m), computed
     from the five lines through that node and its (Theta, Phi) plane only.
     F may be any array-like indexable by numpy (e.g. a memory map)."""
@@ -300,8 +356,11 @@ def rhs_at(F, g, kappa, sigma, eta, idx, bc=True, scattering=True):
     ka, si, et = (float(np.asarray(c)[e, j, l, k]) for c in (kappa, sigma, eta))
     if not scattering:
         si = 0.0
-    mean = np.sum(plane * g.w_Theta[:, None]) * (2.0 * np.pi / nPh) / (4.0 * np.pi)
-    out = -LF + et - (ka + si) * plane[i, m] + si * mean
+    if is_isotropic(kernel):
+        inscat = np.sum(plane * g.w_Theta[:, None]) * (2.0 * np.pi / nPh) / (4.0 * np.pi)
+    else:
+        inscat = scattering_matrix(g, kernel)[i * nPh + m] @ plane.reshape(-1)
+    out = -LF + et - (ka + si) * plane[i, m] + si * inscat
     if bc:
         cT = np.cos(Th)
         if (j == 0 and cT > 0) or (j == g.n_r - 1 and cT < 0):

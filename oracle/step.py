@@ -25,6 +25,8 @@ class Physics:
     bc: bool = True
     scattering: bool = True
     filt: bool = False
+    # phase function p(mu) = (1 - c2/3) + c1 mu + c2 mu^2 as (c1, c2); None = isotropic
+    kernel: tuple = None
 
     @staticmethod
     def vacuum(g, bc=True):
@@ -33,7 +35,7 @@ class Physics:
 
 
 def rhs(F, g, p):
-    return ops.rhs(F, g, p.kappa, p.sigma, p.eta, bc=p.bc, scattering=p.scattering)
+    return ops.rhs(F, g, p.kappa, p.sigma, p.eta, bc=p.bc, scattering=p.scattering, kernel=p.kernel)
 
 
 def rk4_stages(y, g, p, dt):

@@ -5,8 +5,10 @@ explicit index loops from the 1D matrices (which are pinned on their own) and
 coefficients evaluated with the math module, following the definitions:
 Eq. (Liouvsph) for the operator, the DFS identities
 F(-theta, phi, Theta, Phi) = F(theta, phi + pi, Theta, Phi + pi) and
-F(-Theta, Phi) = F(Theta, Phi + pi) for the theta and Theta lines, the isotropic
-collision term and the inflow mask.  Sizes are kept at a few hundred nodes.
+F(-Theta, Phi) = F(Theta, Phi + pi) for the theta and Theta lines, the collision
+term (in-scattering written out as the double sum over directions of the phase
+function p(omega . omega') = c0 + c1 mu + c2 mu^2, with omega from the angles by
+the math module) and the inflow mask.  Sizes are kept at a few hundred nodes.
 """
 
 import math
@@ -16,7 +18,11 @@ import numpy as np
 from oracle import grid as og
 
 
-def assemble(g, kappa=None, sigma=None, bc=True, with_L=True, dtype=float):
+def _omega(Th, Ph):
+    return (math.cos(Th), math.sin(Th) * math.cos(Ph), math.sin(Th) * math.sin(Ph))
+
+
+def assemble(g, kappa=None, sigma=None, bc=True, with_L=True, dtype=float, kernel=None):
     shp = g.shape
     n = int(np.prod(shp))
     A = np.zeros((n, n), dtype=dtype)
@@ -66,9 +72,15 @@ def assemble(g, kappa=None, sigma=None, bc=True, with_L=True, dtype=float):
                                 ka = kappa[e, j, l, k]
                                 si = sigma[e, j, l, k]
                                 A[row, row] -= ka + si
+                                c1, c2 = kernel if kernel is not None else (0.0, 0.0)
+                                c0 = 1.0 - c2 / 3.0
+                                om = _omega(Th, Ph)
                                 for ii in range(nTh):
                                     for mm in range(nPh):
-                                        A[row, idx[e, j, l, k, ii, mm]] += si * wT[ii] * (2 * math.pi / nPh) / (4 * math.pi)
+                                        op = _omega((ii + 0.5) * math.pi / nTh, 2 * math.pi * mm / nPh)
+                                        mu = om[0] * op[0] + om[1] * op[1] + om[2] * op[2]
+                                        ph = c0 + c1 * mu + c2 * mu * mu
+                                        A[row, idx[e, j, l, k, ii, mm]] += si * ph * wT[ii] * (2 * math.pi / nPh) / (4 * math.pi)
     return A
 
 
