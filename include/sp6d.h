@@ -103,11 +103,25 @@ sp6_status sp6_get_nodes(sp6_grid grid, double* r, double* theta, double* phi, d
 sp6_status sp6_get_weights(sp6_grid grid, double* w_r, double* w_theta, double* w_phi,
                            double* w_Theta, double* w_Phi);
 
-/* Copy kappa (absorption), sigma (isotropic scattering) and eta (emission), each
- * [n_eps][n_r][n_theta][n_phi] on the device, into library storage (stream
+/* Copy kappa (absorption), sigma (total scattering opacity) and eta (emission),
+ * each [n_eps][n_r][n_theta][n_phi] on the device, into library storage (stream
  * ordered; the caller may reuse its buffers afterwards). */
 sp6_status sp6_set_coefficients(sp6_grid grid, const double* kappa, const double* sigma,
                                 const double* eta);
+
+/* Phase function of coherent scattering (Eq. sigmadif): the in-scattered term is
+ * sigma (K F)(omega) with (K F)(omega) = sum over the (Theta, Phi) nodes omega' of
+ * w(omega') p(omega . omega') F(omega'), w = w_i (2 pi / n_Phi) / (4 pi) (Fejer
+ * weights in cos Theta), and p(mu) = c0 + c1 mu + c2 mu^2 with c0 = 1 - c2 / 3, so
+ * that p averages to one over the sphere and sigma is the total scattering
+ * opacity.  c1 = c2 = 0 (the default) is isotropic scattering (Eq. sigman with
+ * B = 0); Eq. sigman gives c1 = B / A (Eqs. crossnun, crossnup: -1/3 neutrons,
+ * -1/10 protons); Thomson scattering (Eq. sigmaTh, normalised as the kernel of
+ * App. B, Eq. speccons) is c1 = 0, c2 = 3/4.  Takes effect on handles created with
+ * scattering = 1, for sp6_rhs, sp6_step and sp6_adjoint_step.  SP6_ERR_ARG if c1 or
+ * c2 is not finite or p is negative somewhere on [-1, 1]; the handle keeps its
+ * previous kernel then. */
+sp6_status sp6_set_scattering_kernel(sp6_grid grid, double c1, double c2);
 
 /* Inflow planes [n_eps][n_theta][n_phi][n_Theta][n_Phi] at r_in and r_out (device);
  * only the incoming half (cos Theta > 0 at r_in, < 0 at r_out) is used.

@@ -3,6 +3,7 @@
 // adjoint_step.  No exception crosses the interface.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -378,6 +379,10 @@ sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
   g->c.eta = g->eta;
   g->c.g_in = g->g_in;
   g->c.g_out = g->g_out;
+  g->c.pc0 = 1.0;
+  g->c.pc1 = 0.0;
+  g->c.pc2 = 0.0;
+  g->c.aniso = 0;
   // host tables must stay alive until the copies are done
   if ((e = hipStreamSynchronize(g->stream)) != hipSuccess) goto fail_hip;
   *out = g;
@@ -439,6 +444,24 @@ sp6_status sp6_set_coefficients(sp6_grid g, const double* kappa, const double* s
   HIP_TRY(hipMemcpyAsync(g->sigma, sigma, cb, hipMemcpyDeviceToDevice, g->stream), "copy sigma");
   HIP_TRY(hipMemcpyAsync(g->eta, eta, cb, hipMemcpyDeviceToDevice, g->stream), "copy eta");
   g->coeffs_set = true;
+  return SP6_OK;
+}
+
+sp6_status sp6_set_scattering_kernel(sp6_grid g, double c1, double c2) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (!std::isfinite(c1) || !std::isfinite(c2)) return fail(SP6_ERR_ARG, "c1 and c2 must be finite");
+  const double c0 = 1.0 - c2 / 3.0;
+  auto p = [&](double mu) { return c0 + c1 * mu + c2 * mu * mu; };
+  double pmin = std::min(p(-1.0), p(1.0));
+  if (c2 > 0.0) {
+    const double mu = -c1 / (2.0 * c2);
+    if (mu > -1.0 && mu < 1.0) pmin = std::min(pmin, p(mu));
+  }
+  if (pmin < 0.0) return fail(SP6_ERR_ARG, "phase function p(mu) = c0 + c1 mu + c2 mu^2 is negative on [-1, 1]");
+  g->c.pc0 = c0;
+  g->c.pc1 = c1;
+  g->c.pc2 = c2;
+  g->c.aniso = (c1 != 0.0 || c2 != 0.0) ? 1 : 0;
   return SP6_OK;
 }
 

@@ -104,6 +104,70 @@ SP6_DEV double line_coef(bool isTh, int q, int li, double inv_r, double cot_th, 
 }
 
 // ---------------------------------------------------------------------------
+// anisotropic scattering, p(mu) = c0 + c1 mu + c2 mu^2.  K F needs ten angular
+// moments of the plane: (sum w F, sum w omega F, sum w omega omega F) with
+// omega = (cos Theta, sin Theta cos Phi, sin Theta sin Phi), tensor components
+// ordered xx, yy, zz, xy, xz, yz.  A Phi row contributes through its Fourier sums
+// S0, C1, S1, C2, S2 (of F, cos Phi F, sin Phi F, cos 2Phi F, sin 2Phi F) with the
+// row weight wr.
+
+constexpr int NMOM = 10;
+
+SP6_DEV void row_moments(double wr, double cT, double sT, double S0, double C1, double S1, double C2, double S2,
+                         double* m) {
+  m[0] = wr * S0;
+  m[1] = wr * cT * S0;
+  m[2] = wr * sT * C1;
+  m[3] = wr * sT * S1;
+  m[4] = wr * cT * cT * S0;
+  m[5] = 0.5 * wr * sT * sT * (S0 + C2);
+  m[6] = 0.5 * wr * sT * sT * (S0 - C2);
+  m[7] = wr * cT * sT * C1;
+  m[8] = wr * cT * sT * S1;
+  m[9] = 0.5 * wr * sT * sT * S2;
+}
+
+// Fourier sums of one Phi row read through ld(q), q = m
+template <int NF, typename Load>
+SP6_DEV void row_fourier(const double* cP, const double* sP, Load&& ld, double& S0, double& C1, double& S1, double& C2,
+                         double& S2) {
+  S0 = C1 = S1 = C2 = S2 = 0.0;
+#pragma unroll 4
+  for (int q = 0; q < NF; ++q) {
+    const double v = ld(q), c = cP[q], sn = sP[q];
+    S0 += v;
+    C1 += c * v;
+    S1 += sn * v;
+    C2 += (c * c - sn * sn) * v;
+    S2 += 2.0 * sn * c * v;
+  }
+}
+
+// c0 m0 + c1 omega . J + c2 omega . M . omega
+SP6_DEV double phase_contract(const KCoef& cf, const double* m, double ox, double oy, double oz) {
+  const double dJ = ox * m[1] + oy * m[2] + oz * m[3];
+  const double dM = ox * ox * m[4] + oy * oy * m[5] + oz * oz * m[6] +
+                    2.0 * (ox * oy * m[7] + ox * oz * m[8] + oy * oz * m[9]);
+  return cf.pc0 * m[0] + cf.pc1 * dJ + cf.pc2 * dM;
+}
+
+// sum over omega of u(omega) (K Y)(omega) from the unweighted moments U of u and
+// the weighted moments M of Y: c0 M0 U0 + c1 J.U1 + c2 M:U2
+SP6_DEV double phase_pair(const KCoef& cf, const double* M, const double* U) {
+  const double dJ = M[1] * U[1] + M[2] * U[2] + M[3] * U[3];
+  const double dM = M[4] * U[4] + M[5] * U[5] + M[6] * U[6] + 2.0 * (M[7] * U[7] + M[8] * U[8] + M[9] * U[9]);
+  return cf.pc0 * M[0] * U[0] + cf.pc1 * dJ + cf.pc2 * dM;
+}
+
+// sum of v over the NT Phi-row lanes of a plane (lanes differing in their low bits)
+template <int NT>
+SP6_DEV double plane_rows_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < NT; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
 // forward: L F (partial), right-hand side, or one RK4 stage.
 // Persistent workgroups walk over groups of NPW planes; while the lines and the
 // epilogue of one group are computed, the global loads of the next group are in
@@ -117,13 +181,15 @@ struct PlaneInfo {
 // TY: stored type of the stage input, TO: stored type of T and of the next stage
 // input, TC: type of the line derivatives.  The collision term, the inflow mask
 // and the RK update are FP64 in every instantiation.
-template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC>
+// AN: anisotropic scattering (plane moments instead of the angular mean).
+template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC, bool AN>
 __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
   __shared__ TY sY[C::PTSP];
   __shared__ TC sR[2][C::PTSP];
-  __shared__ double sTh[NT], sPh[C::NF], sCT[NT], sWm[NT];
+  __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT], sWm[NT];
   __shared__ PlaneInfo sPl[C::NPW];
+  __shared__ double sMo[AN ? C::NPW : 1][NMOM];
 
   const int tid = threadIdx.x;
   const int npl = int(d.nplanes);
@@ -132,7 +198,10 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
     sCT[tid] = t.cos_Th[tid];
     sWm[tid] = t.wmean[tid];
   }
-  if (tid < C::NF) sPh[tid] = t.sin_Ph[tid];
+  if (tid < C::NF) {
+    sPh[tid] = t.sin_Ph[tid];
+    sCP[tid] = t.cos_Ph[tid];
+  }
   const bool useTh = a.terms & 8u, usePh = a.terms & 16u;
   const bool needT = a.T != nullptr;
   // ynext may be Yin itself (stages 2 and 3 update the stage buffer in place,
@@ -230,16 +299,34 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       const LineMap<NT> lm = line_map<NT>(pl, li);
       const double inv_r = sPl[pl].inv_r, cot_th = sPl[pl].cot_th;
       if (scat && part == 0) {
-        // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
-        double s = 0.0;
-        if (!isTh) {
+        if constexpr (AN) {
+          // the ten moments (FP64), reduced over the NT Phi lanes of the plane
+          double m[NMOM];
 #pragma unroll
-          for (int q = 0; q < C::L; ++q) s += double(sY[lm.idx(q)]);
-          s *= sWm[li - NT];
+          for (int k = 0; k < NMOM; ++k) m[k] = 0.0;
+          if (!isTh) {
+            const int i = li - NT;
+            double S0, C1, S1, C2, S2;
+            row_fourier<C::NF>(sCP, sPh, [&](int q) { return double(sY[lm.idx(q)]); }, S0, C1, S1, C2, S2);
+            row_moments(sWm[i], sCT[i], sTh[i], S0, C1, S1, C2, S2, m);
+          }
+#pragma unroll
+          for (int k = 0; k < NMOM; ++k) m[k] = plane_rows_sum<NT>(m[k]);
+          if (li == NT) {
+#pragma unroll
+            for (int k = 0; k < NMOM; ++k) sMo[pl][k] = m[k];
+          }
+        } else {
+          // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
+          double s = 0.0;
+          if (!isTh) {
+#pragma unroll
+            for (int q = 0; q < C::L; ++q) s += double(sY[lm.idx(q)]);
+            s *= sWm[li - NT];
+          }
+          s = plane_rows_sum<NT>(s);
+          if (li == NT) sPl[pl].mean = s;
         }
-#pragma unroll
-        for (int off = 1; off < NT; off <<= 1) s += __shfl_xor(s, off, 64);
-        if (li == NT) sPl[pl].mean = s;
       }
       TC* out = sR[isTh ? 0 : 1];
       // the line is streamed from LDS against the transposed table instead of
@@ -268,7 +355,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       const int iTh = (p % C::PLANE) / C::NF;
       const PlaneInfo& pi = sPl[pl];
       const double Yv = double(sY[lp]);
-      double k = -LY + pi.eta - (pi.kappa + pi.sigma) * Yv + pi.sigma * pi.mean;
+      double inscat = pi.mean;
+      if constexpr (AN) {
+        const int m = p % C::NF;
+        inscat = phase_contract(cf, sMo[pl], sCT[iTh], sTh[iTh] * sCP[m], sTh[iTh] * sPh[m]);
+      }
+      double k = -LY + pi.eta - (pi.kappa + pi.sigma) * Yv + pi.sigma * inscat;
       if (d.bc && ((pi.j == 0 && sCT[iTh] > 0.0) || (pi.j == d.n_r - 1 && sCT[iTh] < 0.0))) k = 0.0;
       if (a.mode == PM_RHS) {
         a.out[gp] = k;
@@ -286,12 +378,13 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
 
 // ---------------------------------------------------------------------------
 // transpose: one adjoint stage, or L^T only (lt_out).
-//   u = M (xs x);  a = -(T + Theta^T + Phi^T) - (kappa + sigma) u + sigma avg^T u
+//   u = M (xs x);  a = -(T + Theta^T + Phi^T) - (kappa + sigma) u + sigma K^T u
 //   lacc = (laccsrc or lam) + a;  kbnext = ka lam + kb a
-//   per plane: g_kappa -= sum u Y_s, g_eta += sum u, g_sigma += <Y_s> sum u - sum u Y_s
+//   per plane: g_kappa -= sum u Y_s, g_eta += sum u, g_sigma += sum u (K Y_s) - sum u Y_s
+//   (K = avg for isotropic scattering: sum u (K Y_s) = <Y_s> sum u)
 // Transposed line: v_q = coef_q u_q; z = D v; result_q = -z_q (D^T = -D).
 
-template <int NT>
+template <int NT, bool AN>
 __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCoef cf, AdjArgs a,
                                                             double* lt_out) {
   using C = PC<NT>;
@@ -299,7 +392,8 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
   __shared__ double sY[C::PTSP];
   __shared__ double sR[2][C::PTSP];
   __shared__ double sRed[C::NPW * NT][3];
-  __shared__ double sTh[NT], sPh[C::NF];
+  __shared__ double sMoU[AN ? C::NPW : 1][NMOM], sMoY[AN ? C::NPW : 1][NMOM];
+  __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT];
 
   const int tid = threadIdx.x;
   const int64_t plane0 = int64_t(blockIdx.x) * C::NPW;
@@ -307,8 +401,14 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
   const int64_t npl = d.nplanes;
   const bool lt = lt_out != nullptr;
   const bool grads = !lt && (a.gk || a.ge || a.gs) && a.Ys;
-  if (tid < NT) sTh[tid] = t.sin_Th[tid];
-  if (tid < C::NF) sPh[tid] = t.sin_Ph[tid];
+  if (tid < NT) {
+    sTh[tid] = t.sin_Th[tid];
+    sCT[tid] = t.cos_Th[tid];
+  }
+  if (tid < C::NF) {
+    sPh[tid] = t.sin_Ph[tid];
+    sCP[tid] = t.cos_Ph[tid];
+  }
 
   double xr[C::PPT], tv[C::PPT], lv[C::PPT], cv[C::PPT];
 #pragma unroll
@@ -356,6 +456,35 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
       sRed[pl * NT + i][1] = suy;
       sRed[pl * NT + i][2] = t.wmean[i] * sy;
     }
+    if constexpr (AN) if (part == 0) {
+      // unweighted moments of u (for K^T u) and weighted moments of Y_s (for the
+      // sigma gradient), reduced over the NT Phi lanes of the plane
+      double mu[NMOM], my[NMOM];
+#pragma unroll
+      for (int k = 0; k < NMOM; ++k) mu[k] = my[k] = 0.0;
+      if (!isTh) {
+        const int i = li - NT;
+        double S0, C1, S1, C2, S2;
+        row_fourier<C::NF>(sCP, sPh, [&](int q) { return sU[lm.idx(q)]; }, S0, C1, S1, C2, S2);
+        row_moments(1.0, sCT[i], sTh[i], S0, C1, S1, C2, S2, mu);
+        if (grads) {
+          row_fourier<C::NF>(sCP, sPh, [&](int q) { return sY[lm.idx(q)]; }, S0, C1, S1, C2, S2);
+          row_moments(t.wmean[i], sCT[i], sTh[i], S0, C1, S1, C2, S2, my);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < NMOM; ++k) {
+        mu[k] = plane_rows_sum<NT>(mu[k]);
+        my[k] = plane_rows_sum<NT>(my[k]);
+      }
+      if (li == NT) {
+#pragma unroll
+        for (int k = 0; k < NMOM; ++k) {
+          sMoU[pl][k] = mu[k];
+          sMoY[pl][k] = my[k];
+        }
+      }
+    }
     double* out = sR[isTh ? 0 : 1];
     eo_pairs_stream<C::L, C::PPW, true, double>(
         line_tab<C::L>(LT_DERIV_T), part * C::PPW,
@@ -381,11 +510,19 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
     const int iTh = (p % C::PLANE) / C::NF;
     double av = -LTu - cf.kappa[pid] * u;
     if (d.scattering) {
-      double su = 0.0;
+      // K^T u at this direction: w(omega') times the phase-weighted sums of u
+      double ktu;
+      if constexpr (AN) {
+        const int m = p % C::NF;
+        ktu = t.wmean[iTh] * phase_contract(cf, sMoU[pl], sCT[iTh], sTh[iTh] * sCP[m], sTh[iTh] * sPh[m]);
+      } else {
+        double su = 0.0;
 #pragma unroll
-      for (int ii = 0; ii < NT; ++ii) su += sRed[pl * NT + ii][0];
+        for (int ii = 0; ii < NT; ++ii) su += sRed[pl * NT + ii][0];
+        ktu = t.wmean[iTh] * su;
+      }
       const double si = cf.sigma[pid];
-      av += si * (t.wmean[iTh] * su - u);
+      av += si * (ktu - u);
     }
     const double lam = a.lam_is_x ? xr[q] : lv[q];
     if (a.laccdst) a.laccdst[gp] = (a.laccsrc ? cv[q] : lam) + av;
@@ -404,7 +541,11 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane_adj(KDims d, KTab t, KCo
       }
       if (a.gk) a.gk[pid] -= suy;
       if (a.ge) a.ge[pid] += su;
-      if (a.gs && d.scattering) a.gs[pid] += my * su - suy;
+      if (a.gs && d.scattering) {
+        double uky = my * su;  // sum over the plane of u (K Y_s)
+        if constexpr (AN) uky = phase_pair(cf, sMoY[pl], sMoU[pl]);
+        a.gs[pid] += uky - suy;
+      }
     }
   }
 }
@@ -465,20 +606,28 @@ unsigned persistent_blocks(const KDims& d, K kernel, int threads, int64_t work) 
   return unsigned(work < cap ? work : cap);
 }
 
-template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC>
+template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC, bool AN>
 void launch_plane_t(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   const int ng = int((d.nplanes + PC<NT>::NPW - 1) / PC<NT>::NPW);
-  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, NY, TY, TO, TC>, PC<NT>::NTHR, ng);
-  k_plane<NT, NA, NY, TY, TO, TC><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
+  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, NY, TY, TO, TC, AN>, PC<NT>::NTHR, ng);
+  k_plane<NT, NA, NY, TY, TO, TC, AN><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
 }
 
 template <int NT, typename TY, typename TO, typename TC>
 void launch_plane_nt(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
-  if (na && ny) launch_plane_t<NT, true, true, TY, TO, TC>(d, t, c, a, s);
-  else if (na) launch_plane_t<NT, true, false, TY, TO, TC>(d, t, c, a, s);
-  else if (ny) launch_plane_t<NT, false, true, TY, TO, TC>(d, t, c, a, s);
-  else launch_plane_t<NT, false, false, TY, TO, TC>(d, t, c, a, s);
+  const bool an = d.scattering && c.aniso && a.mode != PM_APPLY;
+  if (an) {
+    if (na && ny) launch_plane_t<NT, true, true, TY, TO, TC, true>(d, t, c, a, s);
+    else if (na) launch_plane_t<NT, true, false, TY, TO, TC, true>(d, t, c, a, s);
+    else if (ny) launch_plane_t<NT, false, true, TY, TO, TC, true>(d, t, c, a, s);
+    else launch_plane_t<NT, false, false, TY, TO, TC, true>(d, t, c, a, s);
+  } else {
+    if (na && ny) launch_plane_t<NT, true, true, TY, TO, TC, false>(d, t, c, a, s);
+    else if (na) launch_plane_t<NT, true, false, TY, TO, TC, false>(d, t, c, a, s);
+    else if (ny) launch_plane_t<NT, false, true, TY, TO, TC, false>(d, t, c, a, s);
+    else launch_plane_t<NT, false, false, TY, TO, TC, false>(d, t, c, a, s);
+  }
 }
 
 template <int NT>
@@ -507,7 +656,12 @@ hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const Sta
 hipError_t launch_plane_adj(const KDims& d, const KTab& t, const KCoef& c, const AdjArgs& a, hipStream_t s) {
   switch (d.n_Th) {
 #define CASE(N) \
-  case N: k_plane_adj<N><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a, nullptr); break;
+  case N:                                                                                  \
+    if (d.scattering && c.aniso)                                                           \
+      k_plane_adj<N, true><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a, nullptr);  \
+    else                                                                                   \
+      k_plane_adj<N, false><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a, nullptr); \
+    break;
     CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -524,7 +678,7 @@ hipError_t launch_plane_LT(const KDims& d, const KTab& t, const double* G, const
   KCoef c{};
   switch (d.n_Th) {
 #define CASE(N) \
-  case N: k_plane_adj<N><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a, out); break;
+  case N: k_plane_adj<N, false><<<plane_blocks<N>(d), PC<N>::NTHR, 0, s>>>(d, t, c, a, out); break;
     CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
 #undef CASE
     default: return hipErrorInvalidValue;

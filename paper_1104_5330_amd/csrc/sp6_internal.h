@@ -47,6 +47,10 @@ struct KCoef {
   const double* eta;
   const double* g_in;   // [n_eps][n_th][n_ph][plane]
   const double* g_out;
+  // scattering phase function p(mu) = pc0 + pc1 mu + pc2 mu^2; aniso = 0 when
+  // isotropic (pc1 = pc2 = 0, pc0 = 1)
+  double pc0, pc1, pc2;
+  int aniso;
 };
 
 // ---------------------------------------------------------------------------

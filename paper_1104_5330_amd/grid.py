@@ -114,6 +114,11 @@ class Sp6Grid:
         self._call(self.lib.sp6_set_coefficients, _ptr(kappa, "kappa", s), _ptr(sigma, "sigma", s),
                    _ptr(eta, "eta", s))
 
+    def set_scattering_kernel(self, c1=0.0, c2=0.0):
+        """Phase function p(mu) = (1 - c2/3) + c1 mu + c2 mu^2 of the scattering term
+        (isotropic by default; Thomson is c1 = 0, c2 = 3/4)."""
+        self._call(self.lib.sp6_set_scattering_kernel, ctypes.c_double(c1), ctypes.c_double(c2))
+
     def set_inflow(self, g_in=None, g_out=None):
         s = self.plane_shape
         self._call(self.lib.sp6_set_inflow, _ptr(g_in, "g_in", s), _ptr(g_out, "g_out", s))

@@ -1,0 +1,141 @@
+"""GPU parity of anisotropic scattering (phase function p(mu) = c0 + c1 mu +
+c2 mu^2, c0 = 1 - c2/3; Eqs. sigmadif, sigman, sigmaTh and App. B) against the
+FP64 oracle: right-hand side, RK4 steps and the adjoint step, FP64 (1e-12) and
+mixed (1e-5), on shapes from a 2 x 4 plane to a 32 x 64 plane, plus sampled nodes
+of the full-size scattering workload."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import ops, step, adjoint
+from tests.gpu_util import need_gpu, maxrel, to_dev, to_host, oracle_grid, small, banner
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+KERNELS = {"thomson": (0.0, 0.75), "neutron": (-1.0 / 3.0, 0.0), "mixed": (0.4, -0.6)}
+SHAPES = {
+    "tiny": small(3, n_eps=1, n_r=5, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
+    "small": small(3, n_eps=2, n_r=9, n_theta=4, n_phi=8, n_Theta=8, n_Phi=16),
+    "w3_reduced": small(3, n_eps=1, n_r=5),
+    "wide_plane": small(3, n_eps=1, n_r=5, n_theta=2, n_phi=4, n_Theta=32, n_Phi=64),
+}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    import paper_1104_5330_amd  # noqa: F401
+
+
+def setup(cfg, kern, seed=0, precision="fp64"):
+    from paper_1104_5330_amd import Sp6Grid
+    G = Sp6Grid.from_config(cfg, scattering=True, precision=precision)
+    G.set_scattering_kernel(*kern)
+    F = synth.fields.random_state(cfg, seed)
+    k, s, e = synth.fields.random_coeffs(cfg, seed + 1)
+    G.set_coefficients(to_dev(k), to_dev(s), to_dev(e))
+    return G, F, (k, s, e)
+
+
+@pytest.mark.parametrize("kname", list(KERNELS))
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_rhs(name, kname):
+    cfg, kern = SHAPES[name], KERNELS[kname]
+    G, F, (k, s, e) = setup(cfg, kern)
+    got = to_host(G.rhs(to_dev(F)))
+    g = oracle_grid(cfg)
+    want = ops.rhs(F, g, k, s, e, kernel=kern)
+    err = maxrel(got, want)
+    # the kernel must matter for these inputs, so that parity shows it was applied
+    effect = maxrel(ops.rhs(F, g, k, s, e), want)
+    banner(f"scattering rhs {name} {kname}: {err:.2e} (kernel effect {effect:.1e})")
+    assert err <= TOL and effect >= 1e3 * TOL
+
+
+@pytest.mark.parametrize("kname", ["thomson", "mixed"])
+@pytest.mark.parametrize("name", ["tiny", "small", "wide_plane"])
+def test_step_and_adjoint(name, kname):
+    cfg, kern = SHAPES[name], KERNELS[kname]
+    G, F, (k, s, e) = setup(cfg, kern, seed=3)
+    g = oracle_grid(cfg)
+    p = step.Physics(k, s, e, bc=True, scattering=True, kernel=kern)
+    dt = cfg.dt
+    Fd = to_dev(F)
+    G.step(Fd, dt, 3)
+    err = maxrel(to_host(Fd), step.run(F, g, p, dt, 3))
+    lam = synth.fields.random_state(cfg, 8)
+    lam_prev, gk, ge, gs = adjoint.adjoint_step(F, lam, g, p, dt)
+    lam_d = to_dev(lam)
+    z = torch.zeros(cfg.shape[:4], dtype=torch.float64, device="cuda")
+    gkd, ged, gsd = z.clone(), z.clone(), z.clone()
+    G.adjoint_step(to_dev(F), dt, lam_d, gkd, ged, gsd)
+    errs = (maxrel(to_host(lam_d), lam_prev), maxrel(to_host(gkd), gk), maxrel(to_host(ged), ge),
+            maxrel(to_host(gsd), gs))
+    banner(f"scattering step/adjoint {name} {kname}: step {err:.2e}, adjoint {errs}")
+    assert err <= TOL
+    assert errs[0] <= TOL and max(errs[1:]) <= 1e-11
+
+
+def test_mixed_step():
+    cfg, kern = SHAPES["small"], KERNELS["thomson"]
+    G, F, (k, s, e) = setup(cfg, kern, seed=5, precision="mixed")
+    g = oracle_grid(cfg)
+    p = step.Physics(k, s, e, bc=True, scattering=True, kernel=kern)
+    Fd = to_dev(F)
+    G.step(Fd, cfg.dt, 5)
+    err = maxrel(to_host(Fd), step.run(F, g, p, cfg.dt, 5))
+    banner(f"mixed Thomson step vs oracle: {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_back_to_isotropic_and_invalid_kernels():
+    from paper_1104_5330_amd import Sp6Error
+    cfg = SHAPES["small"]
+    G, F, (k, s, e) = setup(cfg, KERNELS["thomson"])
+    G.set_scattering_kernel(0.0, 0.0)
+    got = to_host(G.rhs(to_dev(F)))
+    assert maxrel(got, ops.rhs(F, oracle_grid(cfg), k, s, e)) <= TOL
+    for bad in ((0.0, 6.0), (2.5, 0.0), (float("nan"), 0.0), (0.0, float("inf"))):
+        with pytest.raises(Sp6Error) as ei:
+            G.set_scattering_kernel(*bad)
+        assert ei.value.status == 1  # SP6_ERR_ARG
+    # a rejected kernel leaves the previous one in place
+    got = to_host(G.rhs(to_dev(F)))
+    assert maxrel(got, ops.rhs(F, oracle_grid(cfg), k, s, e)) <= TOL
+
+
+def test_full_size_sampled_thomson():
+    """The scattering workload at full size (8 groups, 33 x 16 x 32 x 16 x 32) with
+    the Thomson kernel: the right-hand side at sampled nodes, one by one."""
+    from paper_1104_5330_amd import Sp6Grid
+    cfg = synth.config(3)
+    kern = KERNELS["thomson"]
+    dev = torch.device("cuda")
+    F0 = synth.fields.shell_state(cfg, device=dev)
+    k, s, e = synth.fields.coefficients(cfg)
+    G = Sp6Grid.from_config(cfg, scattering=True)
+    G.set_scattering_kernel(*kern)
+    G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in (k, s, e)))
+    out = G.rhs(F0)
+    torch.cuda.synchronize()
+    g = oracle_grid(cfg)
+    rng = np.random.default_rng(7)
+    got, want = [], []
+    for _ in range(120):
+        idx = tuple(int(rng.integers(0, n)) for n in cfg.shape)
+        want.append(ops.rhs_at(_Lines(F0), g, k, s, e, idx, kernel=kern))
+        got.append(out[idx].item())
+    err = np.max(np.abs(np.array(got) - np.array(want))) / out.abs().max().item()
+    banner(f"full-size Thomson rhs, 120 sampled nodes: {err:.2e}")
+    assert err <= TOL
+
+
+class _Lines:
+    def __init__(self, t):
+        self.t = t
+
+    def __getitem__(self, idx):
+        return self.t[idx].cpu().numpy()
