@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["all", "fp64", "mixed", "adjoint"], default="all")
+    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "adjoint"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -96,7 +96,7 @@ def kernel_table(kt, P, bpp, total_ms):
     return out
 
 
-def run_steps(cfg, precision, scattering, steps, warmup, F0=None):
+def run_steps(cfg, precision, scattering, steps, warmup, F0=None, kernel=None):
     import torch
     import synth
     from paper_1104_5330_amd import Sp6Grid
@@ -107,6 +107,8 @@ def run_steps(cfg, precision, scattering, steps, warmup, F0=None):
     coeffs = [torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)]
     G = Sp6Grid.from_config(cfg, precision=precision, bc=True, scattering=scattering)
     G.set_coefficients(*coeffs)
+    if kernel is not None:
+        G.set_scattering_kernel(*kernel)
     W = F0.clone()
     G.step(W, cfg.dt, warmup)
     del W
@@ -150,6 +152,24 @@ def form_mixed(args):
         "error_vs_fp64": {"max_rel": err_max, "l2_rel": err_l2, "after_steps": args.steps},
         "hbm_fraction_algorithmic_104B": P * args.steps / (ms / 1e3) * FUSED_MIN_B["mixed"] / (HBM_PEAK_GBS * 1e9),
         "kernels": kernel_table(kt, P, BYTES_MIXED, ms),
+    }
+
+
+def form_thomson(args):
+    """FP64 step of the scattering workload with the Thomson phase function
+    (3/4)(1 + mu^2) instead of isotropic scattering (ten plane moments per stage)."""
+    import synth
+    cfg = synth.config(3)
+    _, _, ms, kt = run_steps(cfg, "fp64", True, args.steps, args.warmup, kernel=(0.0, 0.75))
+    _, _, ms_iso, _ = run_steps(cfg, "fp64", True, args.steps, 0)
+    P = cfg.points
+    return {
+        "workload": cfg.name, "grid": list(cfg.shape),
+        "physics": "emission+absorption+Thomson scattering p(mu) = 3/4 (1 + mu^2)",
+        "value": P * args.steps / (ms / 1e3), "unit": "grid-point updates/s", "ms_per_step": ms / args.steps,
+        "steps": args.steps, "dtype": "f64",
+        "isotropic_same_workload": P * args.steps / (ms_iso / 1e3),
+        "kernels": kernel_table(kt, P, BYTES_FP64, ms),
     }
 
 
@@ -271,6 +291,8 @@ def main():
         forms["fp64"] = {"value": value, "ms_per_step": ms / args.steps}
     if args.form in ("all", "mixed"):
         forms["mixed"] = form_mixed(args)
+    if args.form in ("all", "thomson"):
+        forms["thomson"] = form_thomson(args)
     if args.form in ("all", "adjoint"):
         forms["adjoint"] = form_adjoint(args)
     out["forms"] = forms

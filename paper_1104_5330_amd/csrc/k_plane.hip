@@ -159,11 +159,12 @@ SP6_DEV double phase_pair(const KCoef& cf, const double* M, const double* U) {
   return cf.pc0 * M[0] * U[0] + cf.pc1 * dJ + cf.pc2 * dM;
 }
 
-// sum of v over the NT Phi-row lanes of a plane (lanes differing in their low bits)
-template <int NT>
+// sum of v over N consecutive lanes aligned to N (the NT Phi-row lanes of a plane,
+// or all 2 NT lanes of a plane)
+template <int N>
 SP6_DEV double plane_rows_sum(double v) {
 #pragma unroll
-  for (int off = 1; off < NT; off <<= 1) v += __shfl_xor(v, off, 64);
+  for (int off = 1; off < N; off <<= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
@@ -298,35 +299,64 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
       const bool isTh = li < NT;
       const LineMap<NT> lm = line_map<NT>(pl, li);
       const double inv_r = sPl[pl].inv_r, cot_th = sPl[pl].cot_th;
-      if (scat && part == 0) {
-        if constexpr (AN) {
-          // the ten moments (FP64), reduced over the NT Phi lanes of the plane
-          double m[NMOM];
+      if constexpr (AN) {
+        // the ten moments (FP64).  The wavefronts share the work by Fourier
+        // component of the Phi rows (S0: moments 0, 1, 4; C1: 2, 7; S1: 3, 8; C2 and
+        // S2 with S0: 5, 6, 9); lane li of the plane sums half li div NT of row
+        // i = li mod NT, and each moment is reduced over the 2 NT lanes of the plane
+        const int i = li % NT, q0 = (li / NT) * NT, rb = pl * C::PS + i * C::RS + q0;
+        const double wr = sWm[i], cT = sCT[i], sT = sTh[i];
+        for (int grp = part; grp < 4; grp += C::NW) {
+          if (grp == 0) {
+            double S0 = 0.0;
 #pragma unroll
-          for (int k = 0; k < NMOM; ++k) m[k] = 0.0;
-          if (!isTh) {
-            const int i = li - NT;
-            double S0, C1, S1, C2, S2;
-            row_fourier<C::NF>(sCP, sPh, [&](int q) { return double(sY[lm.idx(q)]); }, S0, C1, S1, C2, S2);
-            row_moments(sWm[i], sCT[i], sTh[i], S0, C1, S1, C2, S2, m);
+            for (int q = 0; q < NT; ++q) S0 += double(sY[rb + q]);
+            const double a0 = plane_rows_sum<2 * NT>(wr * S0), a1 = plane_rows_sum<2 * NT>(wr * cT * S0),
+                         a4 = plane_rows_sum<2 * NT>(wr * cT * cT * S0);
+            if (li == 0) {
+              sMo[pl][0] = a0;
+              sMo[pl][1] = a1;
+              sMo[pl][4] = a4;
+            }
+          } else if (grp == 1 || grp == 2) {
+            const double* tr = grp == 1 ? sCP : sPh;  // cos Phi or sin Phi
+            double S = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) S += tr[q0 + q] * double(sY[rb + q]);
+            const double b0 = plane_rows_sum<2 * NT>(wr * sT * S), b1 = plane_rows_sum<2 * NT>(wr * cT * sT * S);
+            if (li == 0) {
+              sMo[pl][grp == 1 ? 2 : 3] = b0;
+              sMo[pl][grp == 1 ? 7 : 8] = b1;
+            }
+          } else {
+            double S0 = 0.0, C2 = 0.0, S2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+              const double v = double(sY[rb + q]), c = sCP[q0 + q], sn = sPh[q0 + q];
+              S0 += v;
+              C2 += (c * c - sn * sn) * v;
+              S2 += 2.0 * sn * c * v;
+            }
+            const double f = 0.5 * wr * sT * sT;
+            const double c5 = plane_rows_sum<2 * NT>(f * (S0 + C2)), c6 = plane_rows_sum<2 * NT>(f * (S0 - C2)),
+                         c9 = plane_rows_sum<2 * NT>(f * S2);
+            if (li == 0) {
+              sMo[pl][5] = c5;
+              sMo[pl][6] = c6;
+              sMo[pl][9] = c9;
+            }
           }
-#pragma unroll
-          for (int k = 0; k < NMOM; ++k) m[k] = plane_rows_sum<NT>(m[k]);
-          if (li == NT) {
-#pragma unroll
-            for (int k = 0; k < NMOM; ++k) sMo[pl][k] = m[k];
-          }
-        } else {
-          // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
-          double s = 0.0;
-          if (!isTh) {
-#pragma unroll
-            for (int q = 0; q < C::L; ++q) s += double(sY[lm.idx(q)]);
-            s *= sWm[li - NT];
-          }
-          s = plane_rows_sum<NT>(s);
-          if (li == NT) sPl[pl].mean = s;
         }
+      } else if (scat && part == 0) {
+        // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
+        double s = 0.0;
+        if (!isTh) {
+#pragma unroll
+          for (int q = 0; q < C::L; ++q) s += double(sY[lm.idx(q)]);
+          s *= sWm[li - NT];
+        }
+        s = plane_rows_sum<NT>(s);
+        if (li == NT) sPl[pl].mean = s;
       }
       TC* out = sR[isTh ? 0 : 1];
       // the line is streamed from LDS against the transposed table instead of
