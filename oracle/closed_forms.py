@@ -12,6 +12,12 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   I = B (1 - exp(-kappa s)), s = r mu + sqrt(R_s^2 - r^2 (1 - mu^2)), mu = cos Theta.
 * B(eps, T) = 2 eps^2 / (exp(eps/T) - 1): the steady state of Eq. (Bose) at zero
   chemical potential, in the same F = gamma^2 f normalisation (Sect. 3.2).
+* Isotropisation in a uniform scattering medium (the experiment of Sect. 5.2,
+  with smooth data): a spatially uniform F(omega) has L F = 0, and the scattering
+  term multiplies its spherical-harmonic part of degree l by -sigma (1 - lambda_l),
+  lambda_l = (1/2) int p(mu) P_l(mu) dmu (Funk-Hecke); classical RK4 multiplies
+  that part by R(-sigma (1 - lambda_l) dt) per step, R(z) = 1 + z + z^2/2 + z^3/6
+  + z^4/24.
 """
 
 import numpy as np
@@ -58,3 +64,33 @@ def homogeneous_sphere(g, kappa, B, R_s):
     k = np.asarray(kappa, np.float64).reshape(-1, 1, 1, 1, 1, 1)
     b = np.asarray(B, np.float64).reshape(-1, 1, 1, 1, 1, 1)
     return np.broadcast_to(b * (1.0 - np.exp(-k * s)), g.shape).copy()
+
+
+def rk4_amplification(z):
+    """Growth factor of one classical RK4 step on y' = lambda y, z = lambda dt."""
+    return 1.0 + z + z * z / 2.0 + z ** 3 / 6.0 + z ** 4 / 24.0
+
+
+def funk_hecke(kernel):
+    """Eigenvalues (lambda_0, lambda_1, lambda_2) of the in-scattering operator for
+    p(mu) = c0 + c1 mu + c2 mu^2, c0 = 1 - c2/3 (kernel = (c1, c2))."""
+    c1, c2 = kernel
+    c0 = 1.0 - c2 / 3.0
+    return c0 + c2 / 3.0, c1 / 3.0, 2.0 * c2 / 15.0
+
+
+def isotropisation(g, a, b, Q, sigma, kernel, dt, n):
+    """F after n RK4 steps from the uniform F0 = a + b . omega + omega . Q . omega
+    (Q symmetric) with kappa = eta = 0, uniform sigma and no inflow mask."""
+    lam = funk_hecke(kernel)
+    R = [rk4_amplification(-sigma * (1.0 - l) * dt) ** n for l in lam]
+    Q = np.asarray(Q, np.float64)
+    tr = np.trace(Q) / 3.0
+    Q2 = Q - tr * np.eye(3)
+
+    def fn(x, y, z, ox, oy, oz):
+        o = (ox, oy, oz)
+        quad = sum(Q2[i, j] * o[i] * o[j] for i in range(3) for j in range(3))
+        return (a + tr) * R[0] + (b[0] * ox + b[1] * oy + b[2] * oz) * R[1] + quad * R[2]
+
+    return on_grid(g, fn)

@@ -139,3 +139,34 @@ class _Lines:
 
     def __getitem__(self, idx):
         return self.t[idx].cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["isotropic", "thomson", "neutron"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_isotropisation_closed_form(name, precision):
+    """Uniform scattering medium (Sect. 5.2's experiment with smooth data): the GPU
+    RK4 solution against the Funk-Hecke/RK4 closed form."""
+    from oracle import closed_forms as cf
+    from paper_1104_5330_amd import Sp6Grid
+    kern = (0.0, 0.0) if name == "isotropic" else KERNELS[name]
+    cfg = small(3, n_eps=2, n_r=9, n_theta=8, n_phi=16, n_Theta=8, n_Phi=16)
+    g = oracle_grid(cfg)
+    a, b = 1.0, (0.5, -0.3, 0.2)
+    Q = np.array([[0.4, 0.1, -0.2], [0.1, -0.1, 0.3], [-0.2, 0.3, 0.25]])
+    F0 = cf.isotropisation(g, a, b, Q, 0.0, kern, 0.0, 0)
+    dt, n = cfg.dt, 20  # a stable step for the Liouville part
+    sig = 0.5 / dt      # sigma dt = 0.5
+    G = Sp6Grid.from_config(cfg, bc=False, scattering=True, precision=precision)
+    G.set_scattering_kernel(*kern)
+    z = np.zeros(cfg.shape[:4])
+    G.set_coefficients(to_dev(z), to_dev(z + sig), to_dev(z))
+    Fd = to_dev(F0)
+    G.step(Fd, dt, n)
+    got = to_host(Fd)
+    want = cf.isotropisation(g, a, b, Q, sig, kern, dt, n)
+    err = maxrel(got, want)
+    p = step.Physics(z, z + sig, z, bc=False, scattering=True, kernel=kern)
+    par = maxrel(got, step.run(F0, g, p, dt, n))
+    banner(f"isotropisation {name} {precision}: closed form {err:.2e}, oracle {par:.2e}")
+    bound = TOL if precision == "fp64" else 1e-5
+    assert err <= bound and par <= bound

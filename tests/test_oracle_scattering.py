@@ -130,3 +130,24 @@ def test_rhs_at_with_kernel():
     for idx in [(0, 0, 0, 0, 0, 0), (1, 4, 3, 7, 3, 7), (1, 2, 1, 5, 2, 3)]:
         v = ops.rhs_at(F, g, kappa, sigma, eta, idx, kernel=KERNELS["thomson"])
         assert v == pytest.approx(full[idx], rel=1e-12, abs=1e-13)
+
+
+@pytest.mark.parametrize("name", ["isotropic", "thomson", "neutron", "mixed"])
+def test_isotropisation_closed_form(name):
+    """Sect. 5.2's uniform-medium experiment with smooth data: the RK4 solution is
+    the Funk-Hecke/RK4 closed form (L F = 0 for F depending on omega only)."""
+    from oracle import closed_forms as cf
+    kern = (0.0, 0.0) if name == "isotropic" else KERNELS[name]
+    g = og.make_grid(1, 5, 4, 8, 8, 16)
+    a, b = 1.0, (0.5, -0.3, 0.2)
+    Q = np.array([[0.4, 0.1, -0.2], [0.1, -0.1, 0.3], [-0.2, 0.3, 0.25]])
+    F0 = cf.isotropisation(g, a, b, Q, 0.0, kern, 0.0, 0)
+    dt, n = g.dt_default(), 10  # a stable step for the Liouville part
+    sig = 0.5 / dt              # sigma dt = 0.5
+    z = np.zeros(g.shape[:4])
+    p = step.Physics(z, z + sig, z, bc=False, scattering=True, kernel=kern)
+    got = step.run(F0, g, p, dt, n)
+    want = cf.isotropisation(g, a, b, Q, sig, kern, dt, n)
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+    # the isotropic part is conserved; the anisotropic parts decay
+    assert np.max(np.abs(want - F0)) > 1e-3
