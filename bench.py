@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "adjoint"], default="all")
+    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "shell", "adjoint"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -171,6 +171,50 @@ def form_thomson(args):
         "isotropic_same_workload": P * args.steps / (ms_iso / 1e3),
         "kernels": kernel_table(kt, P, BYTES_FP64, ms),
     }
+
+
+def form_shell(args):
+    """The 5D shell problem of Sect. 5.3 (one energy, coherent scattering in a
+    shell with a density profile, Lambert inflow F0 cos(Theta) at r_in, empty at
+    t = 0, angular and radial filters after every step) run to t = 4.2 at optical
+    depths 5 and 0; luminosities J(r_in), J(r_out) and particle number at the end."""
+    import math
+    import torch
+    import synth
+    from paper_1104_5330_amd import Sp6Grid
+
+    dev = torch.device("cuda", 0)
+    out = {}
+    for n in (6, 7):
+        cfg = synth.config(n)
+        steps = math.ceil(cfg.t_end / cfg.dt)
+        G = Sp6Grid.from_config(cfg, scattering=True, filter=2)
+        G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
+        g_in, g_out = (torch.as_tensor(a, device=dev) for a in synth.fields.lambert_inflow(cfg))
+        G.set_inflow(g_in, g_out)
+        F = torch.zeros(cfg.shape, dtype=torch.float64, device=dev)
+        G.project_inflow(F)
+        kt = G.step_timed(F.clone(), cfg.dt, 10)  # per-kernel table on a copy
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        G.step(F, cfg.dt, steps)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop)
+        assert torch.isfinite(F).all()
+        N, J_in, J_out = G.diagnostics(F)
+        P = cfg.points
+        out[f"tau{cfg.tau:g}"] = {
+            "workload": cfg.name, "grid": list(cfg.shape), "t_end": steps * cfg.dt, "steps": steps,
+            "value": P * steps / (ms / 1e3), "unit": "grid-point updates/s", "ms_per_step": ms / steps,
+            "dtype": "f64", "filter": "angular + radial exp(-36 eta^36) after every step",
+            "N": float(N[0]), "J_in": float(J_in[0]), "J_out": float(J_out[0]),
+            # the filter class is four in-place passes (theta, phi, plane, r): 64 B per point
+            "kernels": kernel_table(kt, P, dict(BYTES_FP64, filter=64.0), sum(v[0] for v in kt.values())),
+        }
+        G.close()
+    return out
 
 
 def form_adjoint(args):
@@ -293,6 +337,8 @@ def main():
         forms["mixed"] = form_mixed(args)
     if args.form in ("all", "thomson"):
         forms["thomson"] = form_thomson(args)
+    if args.form in ("all", "shell"):
+        forms["shell"] = form_shell(args)
     if args.form in ("all", "adjoint"):
         forms["adjoint"] = form_adjoint(args)
     out["forms"] = forms

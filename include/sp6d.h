@@ -72,7 +72,10 @@ typedef struct {
   int32_t scattering; /* 0/1: include sigma (<F> - F) */
   int32_t filter;     /* 0: off; 1: exponential filter exp(-36 (|k|/k_max)^36) on every
                          theta, phi, Theta and Phi line after each RK4 step (the
-                         paper only mentions coefficient-space viscosity, App. B) */
+                         paper only mentions coefficient-space viscosity, App. B);
+                         2: the same, then on the Chebyshev expansion of every r
+                         line (the paper treats the radial discontinuity of its
+                         shell problem, Sect. 5.3, by finite differences) */
 } sp6_desc;
 
 /* Host-only check of a descriptor (no GPU needed).  SP6_OK if sp6_create would
@@ -168,7 +171,9 @@ sp6_status sp6_step_timed(sp6_grid grid, double* F, double dt, int32_t nsteps, d
 sp6_status sp6_adjoint_step(sp6_grid grid, const double* F_n, double dt, double* lam,
                             double* grad_kappa, double* grad_eta, double* grad_sigma);
 
-/* Apply the spectral filter once, in place (whatever desc.filter says). */
+/* Apply the spectral filter once, in place: the angular line filters, and the
+ * radial one when desc.filter = 2 (desc.filter = 0 still applies the angular
+ * filters). */
 sp6_status sp6_apply_filter(sp6_grid grid, double* F);
 
 /* Particle number N (App. A Eq. Npho) and fluxes through r_in and r_out

@@ -15,7 +15,8 @@ k_s = rhs(Y_s), the exact transpose of the step is (lam = dLoss/dy1):
 
 and the coefficient gradients are sum_s (d rhs(Y_s) / d coeff)^T kb_s, which need
 the stage inputs Y_s (recomputed from y).  With the filter on, lam is first
-mapped by the filter's transpose (the filter is symmetric).
+mapped by the filter's transpose (the angular line filters are symmetric, the
+radial one is not).
 """
 
 import numpy as np
@@ -31,7 +32,7 @@ def adjoint_step(y, lam, g, p, dt):
     [eps][r][theta][phi] arrays for this step only.
     """
     if p.filt:
-        lam = ops.apply_filter(lam, g)
+        lam = ops.apply_filter_T(lam, g, radial=p.filt_r)
     (Y1, Y2, Y3, Y4), _ = step.rk4_stages(y, g, p, dt)
 
     def AT(x):

@@ -313,9 +313,23 @@ def filter_matrix(n):
     return M / n
 
 
-def apply_filter(F, g):
-    """Filter every theta (DFS), phi, Theta (DFS) and Phi line, in that order.
-    The radial direction is not filtered."""
+def radial_filter_matrix(g):
+    """Nodal form of the same exponential filter on the Chebyshev expansion in r:
+    F = sum_k a_k T_k(x) (interpolation on the CGL nodes, x in [-1, 1]) is mapped
+    to sum_k s(k / (n_r - 1)) a_k T_k(x), s(eta) = exp(-36 eta^36).  With the
+    Vandermonde matrix V_jk = T_k(x_j): M = V diag(s) V^-1.  (The paper filters
+    nothing radially; it treats the radial discontinuity of its shell experiment
+    with finite differences, Sect. 5.3.)"""
+    n = g.n_r
+    x = -np.cos(np.pi * np.arange(n) / (n - 1))
+    V = np.polynomial.chebyshev.chebvander(x, n - 1)
+    s = np.exp(-36.0 * (np.arange(n) / (n - 1.0)) ** 36)
+    return V @ np.diag(s) @ np.linalg.inv(V)
+
+
+def apply_filter(F, g, radial=False):
+    """Filter every theta (DFS), phi, Theta (DFS) and Phi line, in that order,
+    then (radial=True) every r line."""
     Ft = filter_matrix(2 * g.n_theta)
     G = apply_along(Ft, dfs_extend_theta(F, g), AX_TH)
     F = np.take(G, np.arange(g.n_theta), axis=AX_TH)
@@ -324,7 +338,19 @@ def apply_filter(F, g):
     G = apply_along(FT, dfs_extend_Theta(F, g), AX_TTH)
     F = np.take(G, np.arange(g.n_Theta), axis=AX_TTH)
     F = apply_along(filter_matrix(g.n_Phi), F, AX_TPH)
+    if radial:
+        F = apply_along(radial_filter_matrix(g), F, AX_R)
     return F
+
+
+def apply_filter_T(X, g, radial=False):
+    """Transpose of apply_filter: the angular line filters are symmetric and act
+    on other axes than the radial one (their partner maps are shifts by pi, which
+    commute with the circulant filters), so the transpose is the radial matrix
+    transposed, then the angular filters."""
+    if radial:
+        X = apply_along(radial_filter_matrix(g).T, X, AX_R)
+    return apply_filter(X, g)
 
 
 # ---------------------------------------------------------------------------

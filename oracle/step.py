@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 The paper advances its spectral coefficients with second-order Adams-Bashforth
 (Sect. 5.1); this hot path uses classical fourth-order Runge-Kutta instead.
 Inflow data are constant in time, so the stages carry no explicit time.
-The optional filter (ops.apply_filter) is applied after each full step.
+The optional filter (ops.apply_filter, angular lines and optionally r) is applied
+after each full step.
 """
 
 from dataclasses import dataclass
@@ -25,6 +26,8 @@ class Physics:
     bc: bool = True
     scattering: bool = True
     filt: bool = False
+    # with filt: also filter the radial (Chebyshev) lines
+    filt_r: bool = False
     # phase function p(mu) = (1 - c2/3) + c1 mu + c2 mu^2 as (c1, c2); None = isotropic
     kernel: tuple = None
 
@@ -56,7 +59,7 @@ def rk4_step(y, g, p, dt):
     _, (k1, k2, k3, k4) = rk4_stages(y, g, p, dt)
     y1 = y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
     if p.filt:
-        y1 = ops.apply_filter(y1, g)
+        y1 = ops.apply_filter(y1, g, radial=p.filt_r)
     return y1
 
 

@@ -350,7 +350,7 @@ sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
 #define UP(field) \
   if ((e = upload(g, h.field, &t.field)) != hipSuccess) goto fail_hip;
   UP(inv_r) UP(inv_sin_th) UP(cot_th) UP(sin_Th) UP(cos_Th) UP(sin_Ph) UP(cos_Ph) UP(wmean) UP(wflux)
-  UP(Dpad) UP(DpadT) UP(qN) UP(qJ)
+  UP(Dpad) UP(DpadT) UP(Fpad) UP(FpadT) UP(qN) UP(qJ)
 #undef UP
   t.KP = h.KP;
   t.NRP = h.NRP;
@@ -524,7 +524,7 @@ sp6_status sp6_apply_filter(sp6_grid g, double* F) {
   if (sp6_status s = check_grid(g)) return s;
   if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
-  HIP_TRY(launch_filter(g->d, g->t, F, g->stream), "filter");
+  HIP_TRY(launch_filter(g->d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
   return SP6_OK;
 }
 
@@ -593,7 +593,7 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
       if (tm) HIP_TRY(tm->mark(g->stream, KC_PLANE), "event");
     }
     if (g->desc.filter) {
-      HIP_TRY(launch_filter(d, g->t, F, g->stream), "filter");
+      HIP_TRY(launch_filter(d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
       if (tm) HIP_TRY(tm->mark(g->stream, KC_FILTER), "event");
     }
   }
@@ -653,7 +653,7 @@ sp6_status sp6_adjoint_step(sp6_grid g, const double* Fn, double dt, double* lam
   HIP_TRY(ensure(g, &g->KB, B), "allocate scratch");
   HIP_TRY(ensure(g, &g->LACC, B), "allocate scratch");
   const KDims& d = g->d;
-  if (g->desc.filter) HIP_TRY(launch_filter(d, g->t, lam, g->stream), "filter of lam");
+  if (g->desc.filter) HIP_TRY(launch_filter(d, g->t, lam, g->desc.filter == 2 ? 2 : 0, g->stream), "filter of lam");
   // recompute the stage inputs Y2, Y3, Y4 from F_n
   double* Ys[5] = {nullptr, const_cast<double*>(Fn), g->Y2, g->Y3, g->Y4};
   const double cn[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};

@@ -238,6 +238,61 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
 }
 
 // ---------------------------------------------------------------------------
+// radial filter (in place): F := Fr F along every r line, or Fr^T F.  Same
+// FP64 MFMA tiling as the radial term; a wavefront reads all rows of its 16
+// columns before it writes them, so in-place is safe (no restrict).
+
+template <int KS>
+__global__ __launch_bounds__(CB) void k_radial_filter(KDims d, KTab t, double* F, int transpose) {
+  constexpr int NRT = (KS + 3) / 4;
+  constexpr int NWV = CB / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = wave_uniform(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const double* __restrict__ Fp = transpose ? t.FpadT : t.Fpad;
+  double a[NRT][KS];
+#pragma unroll
+  for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+    for (int s = 0; s < KS; ++s) a[rt][s] = Fp[(16 * rt + lr) * t.KP + 4 * s + lk];
+  const int gpe = int(d.M / 16);
+  const int ngroups = gpe * d.n_eps;
+  const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
+  const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
+  const int64_t M = d.M;
+  const int n_r = d.n_r;
+  const uint32_t boff = (uint32_t(lk) * uint32_t(M) + uint32_t(lr)) * 8u;
+  auto at = [&](double* row) { return reinterpret_cast<double*>(reinterpret_cast<char*>(row) + boff); };
+  const int sh_g = __builtin_ctz(gpe);
+  for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
+    const int e = g >> sh_g;
+    const int c0 = (g & (gpe - 1)) * 16;
+    double* Fg = F + (int64_t(e) * n_r * M + c0);
+    double b[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      double* row = Fg + int64_t(4 * s) * M;
+      if (s < KS - 1)
+        b[s] = *at(row);
+      else
+        b[s] = 4 * s + lk < n_r ? *at(row) : 0.0;
+    }
+    v4d acc[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) {
+      acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][s], b[s], acc[rt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rt < NRT - 1 || 16 * rt + lk + 4 * v < n_r) *at(Fg + int64_t(16 * rt + 4 * v) * M) = acc[rt][v];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // filter of theta and phi lines (in place; centro-symmetric matrices)
 
 template <int L>
@@ -559,6 +614,22 @@ hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double*
     else                                                                         \
       launch_radial_t<N, false>(d, t, Y, T, transpose, mask_in, in_scale, s);    \
     break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+    CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16) CASE(17) CASE(18) CASE(19) CASE(20)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_radial(const KDims& d, const KTab& t, double* F, bool transpose, hipStream_t s) {
+  const int64_t ngroups = (d.M / 16) * d.n_eps;
+  int64_t blocks = (ngroups + 3) / 4;
+  const int64_t cap = int64_t(d.ncu) * 8;
+  if (blocks > cap) blocks = cap;
+  switch (t.KP / 4) {
+#define CASE(N) \
+  case N: k_radial_filter<N><<<unsigned(blocks), CB, 0, s>>>(d, t, F, transpose ? 1 : 0); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
     CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16) CASE(17) CASE(18) CASE(19) CASE(20)
 #undef CASE

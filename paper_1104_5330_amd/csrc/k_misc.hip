@@ -125,10 +125,11 @@ hipError_t launch_project(const KDims& d, const KTab& t, const KCoef& c, double*
   return hipGetLastError();
 }
 
-hipError_t launch_filter(const KDims& d, const KTab& t, double* F, hipStream_t s) {
+hipError_t launch_filter(const KDims& d, const KTab& t, double* F, int radial, hipStream_t s) {
   hipError_t e = launch_filter_columns(d, t, F, s);
-  if (e != hipSuccess) return e;
-  return launch_filter_plane(d, t, F, s);
+  if (e == hipSuccess) e = launch_filter_plane(d, t, F, s);
+  if (e == hipSuccess && radial) e = launch_filter_radial(d, t, F, radial == 2, s);
+  return e;
 }
 
 size_t diag_partial_count(const KDims& d) { return size_t(d.n_eps) * d.n_r * d.n_th * 3; }

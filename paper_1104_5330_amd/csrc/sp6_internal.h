@@ -34,6 +34,8 @@ struct KTab {
   const double* wflux;       // [n_Th]  w_i (2 pi / n_Ph) cos(Theta_i) where cos > 0, else 0
   const double* Dpad;        // radial matrix, zero padded [NRP][KP]
   const double* DpadT;       // its transpose, same padding
+  const double* Fpad;        // radial filter matrix, same padding
+  const double* FpadT;       // its transpose
   const double* qN;          // [n_r * n_th * n_Th] weights of the particle number
   const double* qJ;          // [n_th * n_Th] weights of the boundary flux (without r^2)
   // mixed precision copies
@@ -61,7 +63,7 @@ struct HostTables {
   std::vector<double> w_r, w_th, w_ph, w_Th, w_Ph;
   std::vector<double> Dr;  // n_r x n_r, row major
   std::vector<double> inv_r, inv_sin_th, cot_th, sin_Th, cos_Th, sin_Ph, cos_Ph, wmean, wflux;
-  std::vector<double> Dpad, DpadT;
+  std::vector<double> Dpad, DpadT, Fpad, FpadT;
   std::vector<double> qN, qJ;
   int KP = 0, NRP = 0;
 };
@@ -137,7 +139,10 @@ hipError_t launch_plane_LT(const KDims& d, const KTab& t, const double* G, const
                            double* out, hipStream_t s);
 
 // filter, projection, diagnostics
-hipError_t launch_filter(const KDims& d, const KTab& t, double* F, hipStream_t s);
+// the angular line filters, then (radial = 1) the radial filter or (radial = 2)
+// its transpose, in place
+hipError_t launch_filter(const KDims& d, const KTab& t, double* F, int radial, hipStream_t s);
+hipError_t launch_filter_radial(const KDims& d, const KTab& t, double* F, bool transpose, hipStream_t s);
 hipError_t launch_project(const KDims& d, const KTab& t, const KCoef& c, double* F, hipStream_t s);
 hipError_t launch_diag(const KDims& d, const KTab& t, const double* F, double* partial, double r_in2,
                        double r_out2, double* out3, hipStream_t s);

@@ -122,7 +122,7 @@ std::string validate_desc(const sp6_desc& d, sp6_status* code) {
   if (d.precision != SP6_FP64 && d.precision != SP6_MIXED) return "precision must be SP6_FP64 or SP6_MIXED";
   if (d.bc != 0 && d.bc != 1) return "bc must be 0 or 1";
   if (d.scattering != 0 && d.scattering != 1) return "scattering must be 0 or 1";
-  if (d.filter != 0 && d.filter != 1) return "filter must be 0 or 1";
+  if (d.filter < 0 || d.filter > 2) return "filter must be 0, 1 or 2";
   *code = SP6_OK;
   return "";
 }
@@ -190,6 +190,30 @@ void build_host_tables(const sp6_desc& d, HostTables& t) {
       t.Dpad[size_t(i) * t.KP + j] = D[size_t(i) * nr + j];
       t.DpadT[size_t(i) * t.KP + j] = D[size_t(j) * nr + i];
     }
+
+  // radial filter: exp(-36 (k/N)^36) on the Chebyshev interpolant of an r line,
+  // Fr = V diag(s) V^-1 with V_jk = T_k(x_j) = (-1)^k cos(pi k j / N) on the
+  // ascending nodes x_j = -cos(pi j / N), and the discrete orthogonality of the
+  // CGL nodes for V^-1: (V^-1)_kj = 2 T_k(x_j) / (N c_k c_j), c_0 = c_N = 2, else 1
+  {
+    auto Tkj = [&](int k, int j) { return ((k & 1) ? -1.0 : 1.0) * std::cos(M_PI * double(k) * j / N); };
+    auto c = [&](int i) { return (i == 0 || i == N) ? 2.0 : 1.0; };
+    std::vector<double> Fr(size_t(nr) * nr, 0.0);
+    for (int k = 0; k < nr; ++k) {
+      const double sk = std::exp(-36.0 * std::pow(double(k) / N, 36.0)) * 2.0 / (N * c(k));
+      for (int i = 0; i < nr; ++i) {
+        const double a = Tkj(k, i) * sk;
+        for (int j = 0; j < nr; ++j) Fr[size_t(i) * nr + j] += a * Tkj(k, j) / c(j);
+      }
+    }
+    t.Fpad.assign(size_t(t.NRP) * t.KP, 0.0);
+    t.FpadT.assign(size_t(t.NRP) * t.KP, 0.0);
+    for (int i = 0; i < nr; ++i)
+      for (int j = 0; j < nr; ++j) {
+        t.Fpad[size_t(i) * t.KP + j] = Fr[size_t(i) * nr + j];
+        t.FpadT[size_t(i) * t.KP + j] = Fr[size_t(j) * nr + i];
+      }
+  }
 
   // pointwise coefficient factors
   t.inv_r.resize(nr);

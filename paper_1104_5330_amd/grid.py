@@ -35,6 +35,7 @@ class Sp6Grid:
 
     Shapes: states [n_eps, n_r, n_theta, n_phi, n_Theta, n_Phi]; coefficient fields
     [n_eps, n_r, n_theta, n_phi]; inflow planes [n_eps, n_theta, n_phi, n_Theta, n_Phi].
+    filter: 0/False off, 1/True angular line filters, 2 angular and radial.
     """
 
     def __init__(self, n_eps, n_r, n_theta, n_phi, n_Theta, n_Phi, r_in=1.0, r_out=3.0,
@@ -42,7 +43,7 @@ class Sp6Grid:
         self.lib = _lib.load()
         self.desc = Sp6Desc(n_eps, n_r, n_theta, n_phi, n_Theta, n_Phi, float(r_in), float(r_out),
                             {"fp64": _lib.SP6_FP64, "mixed": _lib.SP6_MIXED}[precision], int(bool(bc)),
-                            int(bool(scattering)), int(bool(filter)))
+                            int(bool(scattering)), int(filter))
         self.shape = (n_eps, n_r, n_theta, n_phi, n_Theta, n_Phi)
         self.coef_shape = (n_eps, n_r, n_theta, n_phi)
         self.plane_shape = (n_eps, n_theta, n_phi, n_Theta, n_Phi)

@@ -8,7 +8,11 @@ Five workloads, all on the shell 1 <= r <= 3:
 3. workload 2 plus isotropic scattering sigma = kappa / 2 (mixed precision);
 4. adjoint of the outgoing-flux misfit, 4 groups, (33, 16, 32, 16, 32),
    200 steps, checkpoints every 20;
-5. large: (65, 32, 64, 32, 64), 4 groups, scattering, 50 steps.
+5. large: (65, 32, 64, 32, 64), 4 groups, scattering, 50 steps;
+6, 7. the 5D shell of Sect. 5.3: one energy (coherent scattering only),
+   (33, 16, 32, 16, 32), scattering opacity from the density profile, Lambert
+   inflow F0 cos(Theta) at r_in, an empty shell at t = 0, up to t = 4.2;
+   scattering optical depth 5 (6) and 0 (7).
 
 The time step is 0.2 times the first radial spacing of the
 Chebyshev-Gauss-Lobatto grid (the paper's radial stability limit scales as
@@ -29,11 +33,14 @@ class Config:
     n_Theta: int
     n_Phi: int
     steps: int
-    physics: str  # "vacuum" | "emit_abs" | "scatter"
+    physics: str  # "vacuum" | "emit_abs" | "scatter" | "shell"
     r_in: float = 1.0
     r_out: float = 3.0
     T0: float = 10.0
     kappa0: float = 1.0
+    tau: float = 0.0        # "shell": radial scattering optical depth of the shell
+    F0: float = 1.0         # "shell": Lambert inflow amplitude
+    t_end: float = 0.0      # "shell": physical end time (steps = ceil(t_end / dt))
 
     @property
     def shape(self):
@@ -67,6 +74,8 @@ CONFIGS = {
     3: Config("scatter_33x16x32x16x32_g8", 8, 33, 16, 32, 16, 32, 100, "scatter"),
     4: Config("adjoint_33x16x32x16x32_g4", 4, 33, 16, 32, 16, 32, 200, "emit_abs"),
     5: Config("scatter_65x32x64x32x64_g4", 4, 65, 32, 64, 32, 64, 50, "scatter"),
+    6: Config("shell5d_tau5_33x16x32x16x32", 1, 33, 16, 32, 16, 32, 4362, "shell", tau=5.0, t_end=4.2),
+    7: Config("shell5d_tau0_33x16x32x16x32", 1, 33, 16, 32, 16, 32, 4362, "shell", tau=0.0, t_end=4.2),
 }
 
 

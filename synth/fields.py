@@ -222,6 +222,8 @@ def coefficients(cfg, kappa_s=None):
     eta = kappa B(eps, T0 / r), sigma = kappa / 2 for the "scatter" physics and
     0 otherwise; all zero for "vacuum"."""
     shp = (cfg.n_eps, cfg.n_r, cfg.n_theta, cfg.n_phi)
+    if cfg.physics == "shell":
+        return shell_coefficients(cfg)
     if cfg.physics == "vacuum":
         z = np.zeros(shp)
         return z, z.copy(), z.copy()
@@ -235,6 +237,40 @@ def coefficients(cfg, kappa_s=None):
     sigma = 0.5 * kappa if cfg.physics == "scatter" else np.zeros(shp)
     return (np.ascontiguousarray(kappa, dtype=np.float64), np.ascontiguousarray(sigma, dtype=np.float64),
             np.ascontiguousarray(eta, dtype=np.float64))
+
+
+def shell_density(cfg):
+    """Plasma density of the 5D shell problem (Sect. 5.3), normalised to n0 = 1:
+    n = [1 + 0.1 r sin(theta) cos(phi) cos(theta)] (1 - xi)^8, xi = (r - r_in) /
+    (r_out - r_in).  The printed radial factor [1 - (1 - r/R1)/(1 - r/R2)]^8 is
+    singular at R2; it is read as [1 - (1 - r/R1)/(1 - R2/R1)]^8 = (1 - xi)^8,
+    which is 1 at R1 and vanishes smoothly at R2.  Shape [n_r][n_theta][n_phi]."""
+    r, th, ph, _, _ = nodes(cfg)
+    R = r[:, None, None]
+    T = th[None, :, None]
+    P = ph[None, None, :]
+    xi = (R - cfg.r_in) / (cfg.r_out - cfg.r_in)
+    return (1.0 + 0.1 * R * np.sin(T) * np.cos(P) * np.cos(T)) * (1.0 - xi) ** 8
+
+
+def shell_coefficients(cfg):
+    """(kappa, sigma, eta) of the shell problem: coherent scattering only, sigma =
+    sigma0 n with sigma0 set by the optical depth tau = int sigma0 (1 - xi)^8 dr =
+    sigma0 (r_out - r_in) / 9 along a radius."""
+    shp = (cfg.n_eps, cfg.n_r, cfg.n_theta, cfg.n_phi)
+    sigma0 = 9.0 * cfg.tau / (cfg.r_out - cfg.r_in)
+    sigma = np.ascontiguousarray(np.broadcast_to(sigma0 * shell_density(cfg)[None], shp), dtype=np.float64)
+    z = np.zeros(shp)
+    return z, sigma, z.copy()
+
+
+def lambert_inflow(cfg):
+    """Inflow planes [eps][theta][phi][Theta][Phi]: F0 cos(Theta) at r_in (a
+    Lambertian emitter, Sect. 5.3; only cos(Theta) > 0 enters), zero at r_out."""
+    Th = nodes(cfg)[3]
+    shp = (cfg.n_eps, cfg.n_theta, cfg.n_phi, cfg.n_Theta, cfg.n_Phi)
+    g_in = np.ascontiguousarray(np.broadcast_to((cfg.F0 * np.cos(Th))[:, None], shp), dtype=np.float64)
+    return g_in, np.zeros(shp)
 
 
 def uniform_coefficients(cfg, kappa_val, eta_val, sigma_val=0.0):
