@@ -184,13 +184,14 @@ struct PlaneInfo {
 // and the RK update are FP64 in every instantiation.
 // AN: anisotropic scattering (plane moments instead of the angular mean).
 template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC, bool AN>
-__global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
+__global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((NA && !NY && !AN && sizeof(TC) == 8 && NT == 16) ? 4 : 1))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
   __shared__ TY sY[C::PTSP];
   __shared__ TC sR[2][C::PTSP];
   __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT], sWm[NT];
   __shared__ PlaneInfo sPl[C::NPW];
   __shared__ double sMo[AN ? C::NPW : 1][NMOM];
+  __shared__ double sInvR[SP6_MAX_NR], sCot[32];
 
   const int tid = threadIdx.x;
   const int npl = int(d.nplanes);
@@ -203,6 +204,9 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
     sPh[tid] = t.sin_Ph[tid];
     sCP[tid] = t.cos_Ph[tid];
   }
+  for (int i = tid; i < d.n_r; i += C::NTHR) sInvR[i] = t.inv_r[i];
+  for (int i = tid; i < d.n_th; i += C::NTHR) sCot[i] = t.cot_th[i];
+  __syncthreads();
   const bool useTh = a.terms & 8u, usePh = a.terms & 16u;
   const bool needT = a.T != nullptr;
   // ynext may be Yin itself (stages 2 and 3 update the stage buffer in place,
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
         const uint32_t p = uint32_t(tid + q * C::NTHR);
         yi[q] = Yb[p];
         ti[q] = needT ? Tb[p] : TO(0);
-        if constexpr (NA) ai[q] = Ab[p];
+        if constexpr (NA && NY) ai[q] = Ab[p];
         if constexpr (NY) yo[q] = Xb[p];
       }
     } else {
@@ -243,31 +247,31 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
         const bool ok = plane0 + int(p) / C::PLANE < npl;
         yi[q] = ok ? Yb[p] : TY(0);
         ti[q] = (ok && needT) ? Tb[p] : TO(0);
-        if constexpr (NA) ai[q] = ok ? Ab[p] : 0.0;
+        if constexpr (NA && NY) ai[q] = ok ? Ab[p] : 0.0;
         if constexpr (NY) yo[q] = ok ? Xb[p] : 0.0;
       }
     }
   };
-  // thread tid < NPW keeps the coefficients of plane g NPW + tid
-  auto load_info = [&](int g, PlaneInfo& pi) {
+  // thread tid < NPW keeps the coefficients of plane g NPW + tid (the geometric
+  // factors come from the LDS tables)
+  struct PlaneCoef {
+    double kappa, eta, sigma;
+  };
+  auto load_info = [&](int g, PlaneCoef& pc) {
     if (tid < C::NPW) {
       const int pid = min(g * C::NPW + tid, npl - 1);
-      const int l = (pid >> sh_ph) & (d.n_th - 1);
-      const int j = (pid >> (sh_ph + sh_th)) % d.n_r;
-      pi.inv_r = t.inv_r[j];
-      pi.cot_th = t.cot_th[l];
-      pi.kappa = apply ? 0.0 : cf.kappa[pid];
-      pi.eta = apply ? 0.0 : cf.eta[pid];
-      pi.sigma = scat ? cf.sigma[pid] : 0.0;
-      pi.mean = 0.0;
-      pi.j = j;
-      pi.pad = 0;
+      pc.kappa = apply ? 0.0 : cf.kappa[pid];
+      pc.eta = apply ? 0.0 : cf.eta[pid];
+      pc.sigma = scat ? cf.sigma[pid] : 0.0;
     }
   };
+  // the last stage (acc read, no y) loads acc for the current group after the
+  // group barrier instead of one group ahead: fewer registers
+  constexpr bool NA_AHEAD = NA && NY;
   TY yin[C::PPT];
   TO tn[C::PPT];
-  double an[NA ? C::PPT : 1], yn[NY ? C::PPT : 1];
-  PlaneInfo pin{};
+  double an[NA_AHEAD ? C::PPT : 1], yn[NY ? C::PPT : 1];
+  PlaneCoef pin{};
   int grp = gbeg;
   if (grp < gend) {
     load_group(grp, yin, tn, an, yn);
@@ -277,15 +281,37 @@ __global__ __launch_bounds__(PC<NT>::NTHR) void k_plane(KDims d, KTab t, KCoef c
     const int plane0 = grp * C::NPW;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) sY[C::lds(tid + q * C::NTHR)] = yin[q];
-    if (tid < C::NPW) sPl[tid] = pin;
+    if (tid < C::NPW) {
+      const int pid = min(plane0 + tid, npl - 1);
+      const int l = (pid >> sh_ph) & (d.n_th - 1);
+      const int j = (pid >> (sh_ph + sh_th)) % d.n_r;
+      PlaneInfo pi;
+      pi.inv_r = sInvR[j];
+      pi.cot_th = sCot[l];
+      pi.kappa = pin.kappa;
+      pi.eta = pin.eta;
+      pi.sigma = pin.sigma;
+      pi.mean = 0.0;
+      pi.j = j;
+      pi.pad = 0;
+      sPl[tid] = pi;
+    }
     __syncthreads();
     TO tv[C::PPT];
     double av[NA ? C::PPT : 1], yv[NY ? C::PPT : 1];
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       tv[q] = tn[q];
-      if constexpr (NA) av[q] = an[q];
+      if constexpr (NA_AHEAD) av[q] = an[q];
       if constexpr (NY) yv[q] = yn[q];
+    }
+    if constexpr (NA && !NA_AHEAD) {
+      const double* __restrict__ Ab = a.accsrc + int64_t(plane0) * C::PLANE;
+#pragma unroll
+      for (int q = 0; q < C::PPT; ++q) {
+        const uint32_t p = uint32_t(tid + q * C::NTHR);
+        av[q] = plane0 + int(p) / C::PLANE < npl ? Ab[p] : 0.0;
+      }
     }
     if (grp + 1 < gend) {
       load_group(grp + 1, yin, tn, an, yn);

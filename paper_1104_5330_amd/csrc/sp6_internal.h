@@ -9,6 +9,9 @@
 
 #include "../../include/sp6d.h"
 
+// largest supported n_r (descriptor validation; per-workgroup LDS tables)
+constexpr int SP6_MAX_NR = 80;
+
 // ---------------------------------------------------------------------------
 // sizes and device tables, passed to kernels by value
 

@@ -107,7 +107,7 @@ std::string validate_desc(const sp6_desc& d, sp6_status* code) {
   char buf[256];
   *code = SP6_ERR_SHAPE;
   if (d.n_eps < 1) return "n_eps must be >= 1";
-  if (d.n_r < 3 || d.n_r > 80) return "n_r must be in [3, 80]";
+  if (d.n_r < 3 || d.n_r > SP6_MAX_NR) return "n_r must be in [3, 80]";
   if (!pow2_in(d.n_theta, 2, 32)) return "n_theta must be a power of two in [2, 32]";
   if (!pow2_in(d.n_Theta, 2, 32)) return "n_Theta must be a power of two in [2, 32]";
   if (!pow2_in(d.n_phi, 4, 64)) return "n_phi must be a power of two in [4, 64]";
