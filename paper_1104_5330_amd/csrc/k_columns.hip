@@ -358,6 +358,13 @@ __global__ __launch_bounds__(CB) void k_filter_theta(KDims d, KTab t, double* __
 // partner is col ^ R.  For R < n_Phi / 2 a tile is two runs of R columns of one
 // Theta row, m0 .. m0 + R - 1 and their partners; otherwise whole Theta rows.
 
+// tiles per 128-byte line of a column run (R = CW / 2 values of type TI)
+template <int CW, typename TI>
+constexpr int sphere_group() {
+  constexpr int g = 128 / ((CW / 2) * int(sizeof(TI)));
+  return g < 1 ? 1 : (g > 8 ? 8 : g);
+}
+
 template <int NTH, int CW, typename TC>
 struct SPC {
   static constexpr int NPH = 2 * NTH;
@@ -378,10 +385,11 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
   using C = SPC<NTH, CW, TC>;
   constexpr int L = C::L, NPH = C::NPH;
   __shared__ TC sY[C::NE];
-  // blocks b and b + 8 run on the same XCD; they take tiles 2P and 2P + 1, whose
-  // column runs share 128-byte lines when R = 8
+  // blocks b, b + 8, ..., b + 8 (G - 1) run on the same XCD; they take the G
+  // consecutive tiles whose column runs (R = CW / 2 values) share 128-byte lines
+  constexpr int G = sphere_group<CW, TI>();
   const int b = int(blockIdx.x);
-  const int tile = (b >> 4) * 16 + ((b & 7) << 1) + ((b >> 3) & 1);
+  const int tile = (b / (8 * G)) * (8 * G) + (b % 8) * G + (b / 8) % G;
   if (tile >= ntiles) return;
   const int tpp = d.plane / CW;
   const int ej = tile / tpp, tl = tile - ej * tpp;
@@ -526,17 +534,19 @@ void launch_radial_t(const KDims& d, const KTab& t, const double* Y, double* T, 
   k_radial<KS, ACCUM><<<unsigned(blocks), CB, 0, s>>>(d, t, Y, T, transpose, mask_in, in_scale);
 }
 
-int sphere_cw(const KDims& d, bool mixed) {
+// tile width: 16 columns on both paths (FP32 tiles read 32-byte runs, four
+// tiles per 128-byte line; measured faster than 32-column FP32 tiles)
+int sphere_cw(const KDims& d) {
   if (d.n_ph != 2 * d.n_th || d.n_th > 16) return 0;
-  const int cw = mixed ? 32 : 16;
-  return d.plane < cw ? d.plane : cw;
+  return d.plane < 16 ? d.plane : 16;
 }
 
 template <int NTH, int CW, typename TI, typename TC>
 hipError_t launch_sphere_t(const KDims& d, const KTab& t, const void* Y, void* T, double coef_sign, bool mask_in,
                            double in_scale, hipStream_t s) {
   const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
-  const int64_t nb = (ntiles + 15) / 16 * 16;
+  constexpr int64_t GB = 8 * sphere_group<CW, TI>();
+  const int64_t nb = (ntiles + GB - 1) / GB * GB;
   if (nb > INT32_MAX) return hipErrorInvalidValue;
   k_sphere<NTH, CW, TI, TC><<<unsigned(nb), SPC<NTH, CW, TC>::NTHR, 0, s>>>(
       d, t, static_cast<const TI*>(Y), static_cast<TC*>(T), coef_sign, mask_in, in_scale, int(ntiles));
@@ -579,11 +589,11 @@ hipError_t launch_theta_mixed(const KDims& d, const KTab& t, const void* Y, bool
                : launch_theta_p<double, float>(d, t, Y, T, accum, 1.0, false, 1.0, s);
 }
 
-bool sphere_fusable(const KDims& d, bool mixed) { return sphere_cw(d, mixed) > 0; }
+bool sphere_fusable(const KDims& d, bool) { return sphere_cw(d) > 0; }
 
 hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
                          bool mask_in, double in_scale, hipStream_t s) {
-  switch (sphere_cw(d, false)) {
+  switch (sphere_cw(d)) {
     case 8: return launch_sphere_n<8, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
     case 16: return launch_sphere_n<16, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
     default: return hipErrorInvalidValue;
@@ -592,13 +602,13 @@ hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double*
 
 hipError_t launch_sphere_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T,
                                hipStream_t s) {
-  switch (sphere_cw(d, true)) {
+  switch (sphere_cw(d)) {
     case 8:
       return y_f32 ? launch_sphere_n<8, float, float>(d, t, Y, T, 1.0, false, 1.0, s)
                    : launch_sphere_n<8, double, float>(d, t, Y, T, 1.0, false, 1.0, s);
-    case 32:
-      return y_f32 ? launch_sphere_n<32, float, float>(d, t, Y, T, 1.0, false, 1.0, s)
-                   : launch_sphere_n<32, double, float>(d, t, Y, T, 1.0, false, 1.0, s);
+    case 16:
+      return y_f32 ? launch_sphere_n<16, float, float>(d, t, Y, T, 1.0, false, 1.0, s)
+                   : launch_sphere_n<16, double, float>(d, t, Y, T, 1.0, false, 1.0, s);
     default: return hipErrorInvalidValue;
   }
 }
