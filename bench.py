@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "shell", "adjoint"], default="all")
+    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "shell", "ab2", "adjoint"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -217,6 +217,35 @@ def form_shell(args):
     return out
 
 
+def form_ab2(args):
+    """The paper's own integrator (second-order Adams-Bashforth, Sect. 5.1) on the
+    headline workload: one right-hand side per step instead of four."""
+    import torch
+    import synth
+    from paper_1104_5330_amd import Sp6Grid
+
+    cfg = synth.config(2)
+    dev = torch.device("cuda", 0)
+    G = Sp6Grid.from_config(cfg, scattering=False)
+    G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
+    F = synth.fields.shell_state(cfg, device=dev)
+    H = torch.empty_like(F)
+    G.step_ab2(F, H, cfg.dt, max(args.warmup, 1), start=True)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    G.step_ab2(F, H, cfg.dt, args.steps, start=False)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    assert torch.isfinite(F).all()
+    G.close()
+    P = cfg.points
+    return {"workload": cfg.name, "grid": list(cfg.shape), "steps": args.steps, "dtype": "f64",
+            "value": P * args.steps / (ms / 1e3), "unit": "grid-point updates/s (Adams-Bashforth steps)",
+            "ms_per_step": ms / args.steps, "rhs_per_step": 1}
+
+
 def form_adjoint(args):
     import numpy as np
     import torch
@@ -339,6 +368,8 @@ def main():
         forms["thomson"] = form_thomson(args)
     if args.form in ("all", "shell"):
         forms["shell"] = form_shell(args)
+    if args.form in ("all", "ab2"):
+        forms["ab2"] = form_ab2(args)
     if args.form in ("all", "adjoint"):
         forms["adjoint"] = form_adjoint(args)
     out["forms"] = forms

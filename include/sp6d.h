@@ -153,6 +153,17 @@ sp6_status sp6_rhs(sp6_grid grid, const double* F, double* out);
  * filter if enabled).  Needs coefficients. */
 sp6_status sp6_step(sp6_grid grid, double* F, double dt, int32_t nsteps);
 
+/* nsteps >= 0 steps of the second-order Adams-Bashforth scheme the paper uses
+ * (Sect. 5.1), in place on F: F_{n+1} = F_n + dt (3/2 k_n - 1/2 k_{n-1}),
+ * k_n = right-hand side at F_n.  H (device, state layout, caller-owned, distinct
+ * from F) carries the history H_n = F_n - (dt/2) k_{n-1} between calls:
+ * start = 1 takes the first step with k_{-1} = k_0 (forward Euler) and
+ * initialises H; start = 0 continues from H (same dt as the call that wrote it).
+ * With the filter enabled it acts on F and H after every step.  One right-hand
+ * side evaluation per step.  FP64 handles only (SP6_ERR_STATE on a mixed
+ * handle); needs coefficients. */
+sp6_status sp6_step_ab2(sp6_grid grid, double* F, double* H, double dt, int32_t nsteps, int32_t start);
+
 /* Same as sp6_step, with a HIP event recorded on the handle's stream before the
  * first launch and after every kernel launch.  On return (the stream is
  * synchronised) kernel_ms[c] holds the summed duration and launches[c] the number

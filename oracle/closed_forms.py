@@ -94,3 +94,31 @@ def isotropisation(g, a, b, Q, sigma, kernel, dt, n):
         return (a + tr) * R[0] + (b[0] * ox + b[1] * oy + b[2] * oz) * R[1] + quad * R[2]
 
     return on_grid(g, fn)
+
+
+def isotropisation_ab2(g, a, b, Q, sigma, kernel, dt, n):
+    """The uniform-medium problem of isotropisation() advanced by the
+    Adams-Bashforth scheme with a forward-Euler first step: each degree-l part
+    follows the scalar recurrence u_1 = (1 + z) u_0, u_{n+1} = u_n + z (3/2 u_n -
+    1/2 u_{n-1}), z = -sigma (1 - lambda_l) dt."""
+    lam = funk_hecke(kernel)
+    R = []
+    for l in lam:
+        z = -sigma * (1.0 - l) * dt
+        u_prev, u = 1.0, 1.0
+        for step in range(n):
+            if step == 0:
+                u_prev, u = u, (1.0 + z) * u
+            else:
+                u_prev, u = u, u + z * (1.5 * u - 0.5 * u_prev)
+        R.append(u)
+    Q = np.asarray(Q, np.float64)
+    tr = np.trace(Q) / 3.0
+    Q2 = Q - tr * np.eye(3)
+
+    def fn(x, y, z, ox, oy, oz):
+        o = (ox, oy, oz)
+        quad = sum(Q2[i, j] * o[i] * o[j] for i in range(3) for j in range(3))
+        return (a + tr) * R[0] + (b[0] * ox + b[1] * oy + b[2] * oz) * R[1] + quad * R[2]
+
+    return on_grid(g, fn)

@@ -1,4 +1,5 @@
-"""Oracle time stepping: classical RK4 on dF/dt = -L_sph F + C(F).
+"""Oracle time stepping: classical RK4 on dF/dt = -L_sph F + C(F), and the
+paper's own second-order Adams-Bashforth scheme (Sect. 5.1).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -70,3 +71,21 @@ def run(y, g, p, dt, n_steps, callback=None):
         if callback is not None:
             callback(n + 1, y)
     return y
+
+
+def ab2_run(y, g, p, dt, n_steps, k_prev=None):
+    """n_steps of second-order Adams-Bashforth (the scheme of Sect. 5.1):
+    y_{n+1} = y_n + dt (3/2 k_n - 1/2 k_{n-1}), k_n = rhs(y_n).  Without a
+    previous slope (k_prev None) the first step takes k_{-1} = k_0, i.e. forward
+    Euler (the paper does not state its start).  The filter, if enabled, acts
+    on the state and on the stored slope after every step.  Returns (y, k) with k
+    the stored slope, to continue a run."""
+    for _ in range(n_steps):
+        k = rhs(y, g, p)
+        kp = k if k_prev is None else k_prev
+        y = y + dt * (1.5 * k - 0.5 * kp)
+        if p.filt:
+            y = ops.apply_filter(y, g, radial=p.filt_r)
+            k = ops.apply_filter(k, g, radial=p.filt_r)
+        k_prev = k
+    return y, k_prev

@@ -606,6 +606,47 @@ extern "C" {
 
 sp6_status sp6_step(sp6_grid g, double* F, double dt, int32_t nsteps) { return run_steps(g, F, dt, nsteps, nullptr); }
 
+sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nsteps, int32_t start) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
+  if (start != 0 && start != 1) return fail(SP6_ERR_ARG, "start must be 0 or 1");
+  if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "sp6_step_ab2 needs an FP64 handle");
+  if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
+  if (sp6_status s = check_state_io(g, F, "F", H, "H")) return s;
+  if (nsteps == 0) return SP6_OK;
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  HIP_TRY(ensure(g, &g->T, state_bytes(g)), "allocate scratch");
+  const KDims& d = g->d;
+  for (int32_t n = 0; n < nsteps; ++n) {
+    bool wrote = false;
+    HIP_TRY(column_terms(g, F, 7u, false, false, 1.0, &wrote), "column passes");
+    // one plane pass: with k = rhs(F_n),
+    //   first step: H = F + (dt/2) k, F = F + dt k
+    //   later:      F = H + (3 dt/2) k, H = H + dt k
+    StageArgs a{};
+    a.mode = PM_STAGE;
+    a.terms = 31u;
+    a.Yin = F;
+    a.T = wrote ? g->T : nullptr;
+    a.accdst = H;
+    a.ynext = F;
+    if (start && n == 0) {
+      a.accsrc = nullptr, a.cb = 0.5 * dt;
+      a.ysrc = nullptr, a.cn = dt;
+    } else {
+      a.accsrc = H, a.cb = dt;
+      a.ysrc = H, a.cn = 1.5 * dt;
+    }
+    HIP_TRY(launch_plane(d, g->t, g->c, a, g->stream), "plane pass");
+    if (g->desc.filter) {
+      HIP_TRY(launch_filter(d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
+      HIP_TRY(launch_filter(d, g->t, H, g->desc.filter == 2 ? 1 : 0, g->stream), "filter of H");
+    }
+  }
+  return SP6_OK;
+}
+
 sp6_status sp6_step_timed(sp6_grid g, double* F, double dt, int32_t nsteps, double* kernel_ms, int64_t* launches) {
   if (!kernel_ms || !launches) return fail(SP6_ERR_ARG, "kernel_ms and launches must not be NULL");
   Timer tm;

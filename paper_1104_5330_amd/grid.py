@@ -164,6 +164,13 @@ class Sp6Grid:
                    ms, n)
         return {c: (ms[i], n[i]) for i, c in enumerate(self.KERNEL_CLASSES)}
 
+    def step_ab2(self, F, H, dt, nsteps=1, start=True):
+        """Adams-Bashforth steps in place on F; H carries the history between calls
+        (start=True: forward-Euler first step, H initialised)."""
+        self._call(self.lib.sp6_step_ab2, _ptr(F, "F", self.shape), _ptr(H, "H", self.shape), ctypes.c_double(dt),
+                   ctypes.c_int32(nsteps), ctypes.c_int32(1 if start else 0))
+        return F
+
     def adjoint_step(self, F_n, dt, lam, grad_kappa=None, grad_eta=None, grad_sigma=None):
         s = self.coef_shape
         self._call(self.lib.sp6_adjoint_step, _ptr(F_n, "F_n", self.shape), ctypes.c_double(dt),

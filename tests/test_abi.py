@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_symbols():
     with open(os.path.join(ROOT, "include", "sp6d.h")) as f:
         txt = f.read()
-    return sorted(set(re.findall(r"\b(sp6_[a-z_A-Z]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(sp6_[A-Za-z0-9_]+)\s*\(", txt)))
 
 
 @pytest.fixture(scope="module")

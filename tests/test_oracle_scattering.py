@@ -151,3 +151,26 @@ def test_isotropisation_closed_form(name):
     assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
     # the isotropic part is conserved; the anisotropic parts decay
     assert np.max(np.abs(want - F0)) > 1e-3
+
+
+@pytest.mark.parametrize("name", ["isotropic", "thomson"])
+def test_ab2_isotropisation_closed_form(name):
+    """Adams-Bashforth (Sect. 5.1) on the uniform-medium problem: each degree-l
+    part follows the scalar AB2 recurrence with the Funk-Hecke rate; continuing a
+    run from its returned slope equals one longer run."""
+    from oracle import closed_forms as cf
+    kern = (0.0, 0.0) if name == "isotropic" else KERNELS[name]
+    g = og.make_grid(1, 5, 4, 8, 8, 16)
+    a, b = 1.0, (0.5, -0.3, 0.2)
+    Q = np.array([[0.4, 0.1, -0.2], [0.1, -0.1, 0.3], [-0.2, 0.3, 0.25]])
+    F0 = cf.isotropisation(g, a, b, Q, 0.0, kern, 0.0, 0)
+    dt = g.dt_default()
+    sig = 0.3 / dt
+    z = np.zeros(g.shape[:4])
+    p = step.Physics(z, z + sig, z, bc=False, scattering=True, kernel=kern)
+    got, _ = step.ab2_run(F0, g, p, dt, 12)
+    want = cf.isotropisation_ab2(g, a, b, Q, sig, kern, dt, 12)
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.max(np.abs(want))
+    y5, k5 = step.ab2_run(F0, g, p, dt, 5)
+    y12, _ = step.ab2_run(y5, g, p, dt, 7, k_prev=k5)
+    assert np.max(np.abs(y12 - got)) <= 1e-14 * np.max(np.abs(got))
