@@ -31,6 +31,8 @@ def adjoint_step(y, lam, g, p, dt):
     Returns (dLoss/dy_n, grad_kappa, grad_eta, grad_sigma), the gradients as
     [eps][r][theta][phi] arrays for this step only.
     """
+    if p.radial_implicit:
+        raise NotImplementedError("no adjoint of the radially implicit split step")
     if p.filt:
         lam = ops.apply_filter_T(lam, g, radial=p.filt_r)
     (Y1, Y2, Y3, Y4), _ = step.rk4_stages(y, g, p, dt)

@@ -165,6 +165,39 @@ def apply_L(F, g):
             + c_Th * d_Theta(F, g) + c_Ph * d_Phi(F, g))
 
 
+def apply_L_angular(F, g):
+    """L_sph F without the radial term (the four angular terms of Eq. Liouvsph)."""
+    _, c_th, c_ph, c_Th, c_Ph = liouville_coefficients(g)
+    return c_th * d_theta(F, g) + c_ph * d_phi(F, g) + c_Th * d_Theta(F, g) + c_Ph * d_Phi(F, g)
+
+
+def radial_implicit_matrices(g, dt, bc=True):
+    """Backward-Euler radial advection (the implicit scheme of App. B): for each
+    Theta node, F_new solves (I + dt cos(Theta_i) D_r) F_new = F along every r
+    line, with the inflow row (r_in for cos Theta > 0, r_out for cos Theta < 0)
+    replaced by F_new = F there when bc is True.  Returns the inverses, shape
+    (n_Theta, n_r, n_r)."""
+    out = np.empty((g.n_Theta, g.n_r, g.n_r))
+    for i, Th in enumerate(g.Theta):
+        c = np.cos(Th)
+        A = np.eye(g.n_r) + dt * c * g.D_r
+        if bc:
+            row = 0 if c > 0 else g.n_r - 1
+            A[row] = 0.0
+            A[row, row] = 1.0
+        out[i] = np.linalg.inv(A)
+    return out
+
+
+def apply_radial_implicit(F, g, dt, bc=True):
+    """F_new = B_i F along r for every Theta node i (radial_implicit_matrices)."""
+    B = radial_implicit_matrices(g, dt, bc)
+    out = np.empty_like(F)
+    for i in range(g.n_Theta):
+        out[:, :, :, :, i, :] = apply_along(B[i], F[:, :, :, :, i, :], AX_R)
+    return out
+
+
 def apply_LT(G, g):
     """Exact transpose of apply_L (as a matrix on the nodal values):
     sum over directions of D_dir^T (c_dir * G)."""
@@ -276,11 +309,13 @@ def project_inflow(F, g, g_in=None, g_out=None):
     return F
 
 
-def rhs(F, g, kappa, sigma, eta, bc=True, scattering=True, kernel=None):
+def rhs(F, g, kappa, sigma, eta, bc=True, scattering=True, kernel=None, radial=True):
     """Right-hand side dF/dt = -L_sph F + C(F) (Eqs. Transpfpsph, Transp), set to
-    zero at the inflow nodes when bc is True."""
+    zero at the inflow nodes when bc is True; without the radial term of L_sph
+    when radial is False (the explicit part of the radially implicit split)."""
     s = sigma if scattering else np.zeros_like(np.asarray(sigma, np.float64))
-    out = -apply_L(F, g) + collision(F, g, kappa, s, eta, kernel)
+    LF = apply_L(F, g) if radial else apply_L_angular(F, g)
+    out = -LF + collision(F, g, kappa, s, eta, kernel)
     if bc:
         out = out * inflow_mask(g)
     return out

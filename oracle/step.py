@@ -29,6 +29,9 @@ class Physics:
     filt: bool = False
     # with filt: also filter the radial (Chebyshev) lines
     filt_r: bool = False
+    # split step: RK4 on everything but the radial term, then a backward-Euler
+    # radial substep (the implicit scheme of App. B)
+    radial_implicit: bool = False
     # phase function p(mu) = (1 - c2/3) + c1 mu + c2 mu^2 as (c1, c2); None = isotropic
     kernel: tuple = None
 
@@ -39,7 +42,8 @@ class Physics:
 
 
 def rhs(F, g, p):
-    return ops.rhs(F, g, p.kappa, p.sigma, p.eta, bc=p.bc, scattering=p.scattering, kernel=p.kernel)
+    return ops.rhs(F, g, p.kappa, p.sigma, p.eta, bc=p.bc, scattering=p.scattering, kernel=p.kernel,
+                   radial=not p.radial_implicit)
 
 
 def rk4_stages(y, g, p, dt):
@@ -56,9 +60,12 @@ def rk4_stages(y, g, p, dt):
 
 
 def rk4_step(y, g, p, dt):
-    """y_{n+1} = y + dt/6 (k1 + 2 k2 + 2 k3 + k4), then the filter if enabled."""
+    """y_{n+1} = y + dt/6 (k1 + 2 k2 + 2 k3 + k4), then (radial_implicit) the
+    backward-Euler radial substep, then the filter if enabled."""
     _, (k1, k2, k3, k4) = rk4_stages(y, g, p, dt)
     y1 = y + (dt / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    if p.radial_implicit:
+        y1 = ops.apply_radial_implicit(y1, g, dt, bc=p.bc)
     if p.filt:
         y1 = ops.apply_filter(y1, g, radial=p.filt_r)
     return y1

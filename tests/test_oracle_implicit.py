@@ -1,0 +1,76 @@
+"""Pins of the radially implicit split step of the oracle (the backward-Euler
+Chebyshev advection of App. B for the radial term, RK4 for the rest).
+
+* The backward-Euler collocation solve against exact polynomial algebra: with
+  u the data (degree < n_r) and w(r) = prod over the non-inflow nodes of
+  (r - r_j), the collocation solution is the polynomial q with
+  q + dt c q' = u + alpha w, q = sum_k (-dt c)^k (u + alpha w)^(k) (a finite
+  Neumann series), and alpha fixed by q(inflow) = u(inflow).
+* A step from data depending on r only (L reduces to the radial term, the
+  explicit part vanishes in vacuum) equals the solve alone.
+* A uniform state is kept exactly.
+"""
+
+import numpy as np
+from numpy.polynomial import Chebyshev
+import pytest
+
+from oracle import grid as og, ops, step
+
+
+def _backward_euler_poly(r_nodes, u, dtc, inflow, domain):
+    """Exact polynomial solution of the collocated backward-Euler equation (u a
+    Chebyshev series on the shell, for conditioning)."""
+    others = [x for j, x in enumerate(r_nodes) if j != inflow]
+    w = Chebyshev.fromroots(others, domain=domain)
+
+    def neumann(c):
+        out, term, k = c * 0.0, c, 0
+        while term.degree() >= 0 and k <= c.degree() + 1:
+            out = out + (-dtc) ** k * term
+            if term.degree() == 0:
+                break
+            term = term.deriv()
+            k += 1
+        return out
+
+    qu, qw = neumann(u), neumann(w)
+    r0 = r_nodes[inflow]
+    alpha = (u(r0) - qu(r0)) / qw(r0)
+    return lambda r: qu(r) + alpha * qw(r)
+
+
+@pytest.mark.parametrize("n_r", [5, 9, 17])
+def test_backward_euler_solve_polynomial_exact(n_r):
+    g = og.make_grid(1, n_r, 2, 4, 4, 8)
+    dt = 0.05
+    B = ops.radial_implicit_matrices(g, dt)
+    rng = np.random.default_rng(n_r)
+    dom = [g.r_in, g.r_out]
+    u = Chebyshev(rng.normal(size=n_r - 1), domain=dom)  # degree n_r - 2
+    vals = u(g.r)
+    for i, Th in enumerate(g.Theta):
+        c = np.cos(Th)
+        inflow = 0 if c > 0 else n_r - 1
+        q = _backward_euler_poly(g.r, u, dt * c, inflow, dom)
+        np.testing.assert_allclose(B[i] @ vals, q(g.r), rtol=0, atol=1e-12 * np.max(np.abs(vals)))
+
+
+def test_radial_data_step_is_the_solve():
+    g = og.make_grid(1, 9, 4, 8, 4, 8)
+    rng = np.random.default_rng(0)
+    f = rng.normal(size=g.n_r)
+    F = np.broadcast_to(f[None, :, None, None, None, None], g.shape).copy()
+    z = np.zeros(g.shape[:4])
+    p = step.Physics(z, z, z, bc=True, scattering=False, radial_implicit=True)
+    dt = 0.07
+    got = step.rk4_step(F, g, p, dt)
+    np.testing.assert_allclose(got, ops.apply_radial_implicit(F, g, dt), atol=1e-13)
+
+
+def test_constant_state_is_kept():
+    g = og.make_grid(2, 9, 4, 8, 4, 8)
+    z = np.zeros(g.shape[:4])
+    p = step.Physics(z, z, z, bc=True, scattering=False, radial_implicit=True)
+    F = np.full(g.shape, 2.5)
+    np.testing.assert_allclose(step.run(F, g, p, 0.1, 5), F, atol=1e-13)
