@@ -9,6 +9,8 @@ resident in HBM.  Inputs are synthetic and seeded (no dataset is involved).
 Also measured on the same JSON line ("forms"):
   mixed   : the scattering workload (same grid, sigma = kappa/2) on the mixed path,
             with its error against the FP64 path after the timed steps;
+  implicit: the headline workload with the split step of App. B (backward-Euler
+            radial solve after RK4 on the other terms);
   adjoint : the 4-group workload (same angular grid), 200 steps forward plus the
             checkpointed (every 20) discrete-adjoint backward pass of the
             outgoing-flux misfit; value = forward-equivalent updates (points x 200)
@@ -57,7 +59,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "shell", "ab2", "adjoint"], default="all")
+    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "shell", "ab2", "implicit", "adjoint"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -246,6 +248,35 @@ def form_ab2(args):
             "ms_per_step": ms / args.steps, "rhs_per_step": 1}
 
 
+def form_implicit(args):
+    """The split step of App. B on the headline workload: RK4 on the angular and
+    collision terms, then the backward-Euler radial solve (one MFMA pass with the
+    per-Theta inverse matrices) in place of the four explicit radial passes."""
+    import torch
+    import synth
+    from paper_1104_5330_amd import Sp6Grid
+
+    cfg = synth.config(2)
+    dev = torch.device("cuda", 0)
+    G = Sp6Grid.from_config(cfg, scattering=False)
+    G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
+    F = synth.fields.shell_state(cfg, device=dev)
+    G.step_radial_implicit(F, cfg.dt, max(args.warmup, 1))
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    G.step_radial_implicit(F, cfg.dt, args.steps)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    assert torch.isfinite(F).all()
+    G.close()
+    P = cfg.points
+    return {"workload": cfg.name, "grid": list(cfg.shape), "steps": args.steps, "dtype": "f64", "dt": cfg.dt,
+            "value": P * args.steps / (ms / 1e3), "unit": "grid-point updates/s (split steps)",
+            "ms_per_step": ms / args.steps}
+
+
 def form_adjoint(args):
     import numpy as np
     import torch
@@ -370,6 +401,8 @@ def main():
         forms["shell"] = form_shell(args)
     if args.form in ("all", "ab2"):
         forms["ab2"] = form_ab2(args)
+    if args.form in ("all", "implicit"):
+        forms["implicit"] = form_implicit(args)
     if args.form in ("all", "adjoint"):
         forms["adjoint"] = form_adjoint(args)
     out["forms"] = forms

@@ -153,6 +153,17 @@ sp6_status sp6_rhs(sp6_grid grid, const double* F, double* out);
  * filter if enabled).  Needs coefficients. */
 sp6_status sp6_step(sp6_grid grid, double* F, double dt, int32_t nsteps);
 
+/* nsteps >= 0 steps of the split scheme of App. B, in place on F: one RK4 step of
+ * size dt for the angular terms and the collision term (the radial term left
+ * out), then the radial term by a backward-Euler step, F := B_i F along every r
+ * line of direction node Theta_i, B_i = (I + dt cos(Theta_i) D_r)^-1 with the
+ * inflow row (r_in if cos > 0, r_out if cos < 0) replaced by the identity when
+ * bc = 1; then the filter if enabled.  The radial term sets no step limit.  The
+ * B_i are built on the host (Gauss-Jordan, partial pivoting) and kept on the
+ * device for the last dt used (n_Theta n_r^2 doubles, padded).  SP6_ERR_ARG if a
+ * matrix is singular.  Needs coefficients. */
+sp6_status sp6_step_radial_implicit(sp6_grid grid, double* F, double dt, int32_t nsteps);
+
 /* nsteps >= 0 steps of the second-order Adams-Bashforth scheme the paper uses
  * (Sect. 5.1), in place on F: F_{n+1} = F_n + dt (3/2 k_n - 1/2 k_{n-1}),
  * k_n = right-hand side at F_n.  H (device, state layout, caller-owned, distinct

@@ -68,6 +68,10 @@ struct sp6_grid_s {
   double* diag_out = nullptr;
   float* Yf = nullptr;
   float* Tf = nullptr;
+  // backward-Euler radial matrices for the split step, [n_Theta][NRP][KP], and
+  // the dt they were built for
+  double* Bimp = nullptr;
+  double imp_dt = 0.0;
 
   hipError_t alloc(void** p, size_t n) {
     hipError_t e = hipMalloc(p, n);
@@ -271,7 +275,7 @@ sp6_status check_state_io(sp6_grid g, const void* in, const char* nin, const voi
   return check_distinct(in, nin, out, nout, B, B);
 }
 
-sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm);
+sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit = false);
 
 }  // namespace
 
@@ -532,7 +536,59 @@ sp6_status sp6_apply_filter(sp6_grid g, double* F) {
 
 namespace {
 
-sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm) {
+// the backward-Euler radial matrices (I + dt cos Theta_i D_r, inflow row replaced
+// by the identity) inverted on the host by Gauss-Jordan elimination with partial
+// pivoting, padded like the radial matrix, uploaded once per dt
+sp6_status ensure_radial_implicit(sp6_grid g, double dt) {
+  if (g->Bimp && g->imp_dt == dt) return SP6_OK;
+  const HostTables& h = g->h;
+  const int n = g->desc.n_r, nTh = g->desc.n_Theta;
+  const size_t per = size_t(h.NRP) * h.KP;
+  std::vector<double> pad(per * nTh, 0.0), A(size_t(n) * 2 * n);
+  for (int i = 0; i < nTh; ++i) {
+    const double c = h.cos_Th[i];
+    const int brow = c > 0.0 ? 0 : n - 1;
+    for (int r = 0; r < n; ++r)
+      for (int k = 0; k < 2 * n; ++k) {
+        double v = 0.0;
+        if (k < n) {
+          v = (r == k ? 1.0 : 0.0) + dt * c * h.Dr[size_t(r) * n + k];
+          if (g->desc.bc && r == brow) v = (r == k) ? 1.0 : 0.0;
+        } else {
+          v = (k - n == r) ? 1.0 : 0.0;
+        }
+        A[size_t(r) * 2 * n + k] = v;
+      }
+    for (int col = 0; col < n; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < n; ++r)
+        if (std::fabs(A[size_t(r) * 2 * n + col]) > std::fabs(A[size_t(piv) * 2 * n + col])) piv = r;
+      if (A[size_t(piv) * 2 * n + col] == 0.0) return fail(SP6_ERR_ARG, "backward-Euler radial matrix is singular for this dt");
+      if (piv != col)
+        for (int k = 0; k < 2 * n; ++k) std::swap(A[size_t(piv) * 2 * n + k], A[size_t(col) * 2 * n + k]);
+      const double inv = 1.0 / A[size_t(col) * 2 * n + col];
+      for (int k = 0; k < 2 * n; ++k) A[size_t(col) * 2 * n + k] *= inv;
+      for (int r = 0; r < n; ++r) {
+        if (r == col) continue;
+        const double f = A[size_t(r) * 2 * n + col];
+        if (f != 0.0)
+          for (int k = 0; k < 2 * n; ++k) A[size_t(r) * 2 * n + k] -= f * A[size_t(col) * 2 * n + k];
+      }
+    }
+    for (int r = 0; r < n; ++r)
+      for (int k = 0; k < n; ++k) pad[per * i + size_t(r) * h.KP + k] = A[size_t(r) * 2 * n + n + k];
+  }
+  hipError_t e = hipSuccess;
+  if (!g->Bimp) e = g->alloc(reinterpret_cast<void**>(&g->Bimp), pad.size() * sizeof(double));
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(g->Bimp, pad.data(), pad.size() * sizeof(double), hipMemcpyHostToDevice, g->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);  // pad is a local buffer
+  HIP_TRY(e, "radial matrices");
+  g->imp_dt = dt;
+  return SP6_OK;
+}
+
+sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit) {
   if (sp6_status s = check_grid(g)) return s;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
@@ -548,25 +604,28 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
   } else {
     HIP_TRY(ensure_step_scratch(g), "allocate scratch");
   }
+  if (radial_implicit)
+    if (sp6_status st = ensure_radial_implicit(g, dt)) return st;
   const KDims& d = g->d;
+  const uint32_t cols = radial_implicit ? 6u : 7u;  // without the radial term in the split step
   if (tm) HIP_TRY(tm->mark(g->stream, -1), "event");
   for (int32_t n = 0; n < nsteps; ++n) {
     for (int s = 1; s <= 4; ++s) {
       bool wrote = false;
       StageArgs a{};
       a.mode = PM_STAGE;
-      a.terms = 31u;
+      a.terms = cols | 24u;
       a.mixed = mixed;
       if (mixed) {
         // stage 1 reads the FP64 state; later stages the FP32 stage copy
         const void* Yin = (s == 1) ? static_cast<const void*>(F) : static_cast<const void*>(g->Yf);
-        HIP_TRY(column_terms_mixed(g, Yin, s != 1, 7u, &wrote, tm), "column passes");
+        HIP_TRY(column_terms_mixed(g, Yin, s != 1, cols, &wrote, tm), "column passes");
         a.Yin = Yin;
         a.yin_f32 = s != 1;
         a.T = g->Tf;
       } else {
         const double* Yin = (s == 1) ? F : g->Ybuf;
-        HIP_TRY(column_terms(g, Yin, 7u, false, false, 1.0, &wrote, tm), "column passes");
+        HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm), "column passes");
         a.Yin = Yin;
         a.T = g->T;
       }
@@ -592,6 +651,10 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
       HIP_TRY(launch_plane(d, g->t, g->c, a, g->stream), "plane pass");
       if (tm) HIP_TRY(tm->mark(g->stream, KC_PLANE), "event");
     }
+    if (radial_implicit) {
+      HIP_TRY(launch_radial_implicit(d, g->t, g->Bimp, F, g->stream), "radial solve");
+      if (tm) HIP_TRY(tm->mark(g->stream, KC_RADIAL), "event");
+    }
     if (g->desc.filter) {
       HIP_TRY(launch_filter(d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
       if (tm) HIP_TRY(tm->mark(g->stream, KC_FILTER), "event");
@@ -605,6 +668,10 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
 extern "C" {
 
 sp6_status sp6_step(sp6_grid g, double* F, double dt, int32_t nsteps) { return run_steps(g, F, dt, nsteps, nullptr); }
+
+sp6_status sp6_step_radial_implicit(sp6_grid g, double* F, double dt, int32_t nsteps) {
+  return run_steps(g, F, dt, nsteps, nullptr, true);
+}
 
 sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nsteps, int32_t start) {
   if (sp6_status s = check_grid(g)) return s;

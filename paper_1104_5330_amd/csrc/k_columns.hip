@@ -293,6 +293,77 @@ __global__ __launch_bounds__(CB) void k_radial_filter(KDims d, KTab t, double* F
 }
 
 // ---------------------------------------------------------------------------
+// backward-Euler radial solve of the split step (App. B), in place: every r line
+// of direction node Theta_i is multiplied by B_i, the inverse of I + dt cos(Theta_i)
+// D_r (inflow row replaced by the identity), [n_Th][NRP][KP] zero padded.  A
+// group is 16 columns with the same Theta_i (one MFMA B operand): column m of the
+// n_th n_ph n_Ph columns of node i lies at (m / n_Ph) plane + i n_Ph + m % n_Ph,
+// so 16 lanes read runs of min(n_Ph, 16) contiguous doubles.  Groups are ordered
+// with i slowest, and a wavefront reloads B_i only when i changes.  It reads all
+// rows of its columns before it writes them.
+
+template <int KS>
+__global__ __launch_bounds__(CB) void k_radial_implicit(KDims d, const double* __restrict__ Bimp, int KP,
+                                                        double* F) {
+  constexpr int NRT = (KS + 3) / 4;
+  constexpr int NWV = CB / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave = wave_uniform(threadIdx.x >> 6);
+  const int lr = lane & 15, lk = lane >> 4;
+  const int Q = int(d.M / d.n_Th) >> 4;  // 16-column groups per (eps, Theta_i)
+  const int per_i = Q * d.n_eps;
+  const int ngroups = per_i * d.n_Th;
+  const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
+  const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
+  const int64_t M = d.M;
+  const int n_r = d.n_r;
+  const int sh_Ph = __builtin_ctz(d.n_Ph);
+  const int NRP = 16 * NRT;
+  double a[NRT][KS];
+  int cur = -1;
+  for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
+    const int i = g / per_i;
+    const int rem = g - i * per_i;
+    const int e = rem / Q;
+    const int q = rem - e * Q;
+    if (i != cur) {
+      const double* Bi = Bimp + int64_t(i) * NRP * KP;
+#pragma unroll
+      for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int s = 0; s < KS; ++s) a[rt][s] = Bi[(16 * rt + lr) * KP + 4 * s + lk];
+      cur = i;
+    }
+    const uint32_t m = uint32_t(q * 16 + lr);
+    const uint32_t col = (m >> sh_Ph) * uint32_t(d.plane) + uint32_t(i << sh_Ph) + (m & uint32_t(d.n_Ph - 1));
+    const uint32_t boff = (uint32_t(lk) * uint32_t(M) + col) * 8u;
+    auto at = [&](double* row) { return reinterpret_cast<double*>(reinterpret_cast<char*>(row) + boff); };
+    double* Fg = F + int64_t(e) * n_r * M;
+    double b[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      double* row = Fg + int64_t(4 * s) * M;
+      if (s < KS - 1)
+        b[s] = *at(row);
+      else
+        b[s] = 4 * s + lk < n_r ? *at(row) : 0.0;
+    }
+    v4d acc[NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) {
+      acc[rt] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acc[rt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rt][s], b[s], acc[rt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rt < NRT - 1 || 16 * rt + lk + 4 * v < n_r) *at(Fg + int64_t(16 * rt + 4 * v) * M) = acc[rt][v];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // filter of theta and phi lines (in place; centro-symmetric matrices)
 
 template <int L>
@@ -640,6 +711,23 @@ hipError_t launch_filter_radial(const KDims& d, const KTab& t, double* F, bool t
   switch (t.KP / 4) {
 #define CASE(N) \
   case N: k_radial_filter<N><<<unsigned(blocks), CB, 0, s>>>(d, t, F, transpose ? 1 : 0); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
+    CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16) CASE(17) CASE(18) CASE(19) CASE(20)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_radial_implicit(const KDims& d, const KTab& t, const double* Bimp, double* F, hipStream_t s) {
+  if ((d.M / d.n_Th) % 16 != 0) return hipErrorInvalidValue;
+  const int64_t ngroups = (d.M / 16) * d.n_eps;
+  int64_t blocks = (ngroups + 3) / 4;
+  const int64_t cap = int64_t(d.ncu) * 8;
+  if (blocks > cap) blocks = cap;
+  switch (t.KP / 4) {
+#define CASE(N) \
+  case N: k_radial_implicit<N><<<unsigned(blocks), CB, 0, s>>>(d, Bimp, t.KP, F); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10)
     CASE(11) CASE(12) CASE(13) CASE(14) CASE(15) CASE(16) CASE(17) CASE(18) CASE(19) CASE(20)
 #undef CASE

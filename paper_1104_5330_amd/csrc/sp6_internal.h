@@ -146,6 +146,9 @@ hipError_t launch_plane_LT(const KDims& d, const KTab& t, const double* G, const
 // its transpose, in place
 hipError_t launch_filter(const KDims& d, const KTab& t, double* F, int radial, hipStream_t s);
 hipError_t launch_filter_radial(const KDims& d, const KTab& t, double* F, bool transpose, hipStream_t s);
+// backward-Euler radial solve of the split step: F := B_i F on every r line of
+// direction node Theta_i (Bimp: [n_Th][NRP][KP], zero padded), in place
+hipError_t launch_radial_implicit(const KDims& d, const KTab& t, const double* Bimp, double* F, hipStream_t s);
 hipError_t launch_project(const KDims& d, const KTab& t, const KCoef& c, double* F, hipStream_t s);
 hipError_t launch_diag(const KDims& d, const KTab& t, const double* F, double* partial, double r_in2,
                        double r_out2, double* out3, hipStream_t s);

@@ -154,6 +154,13 @@ class Sp6Grid:
         self._call(self.lib.sp6_step, _ptr(F, "F", self.shape), ctypes.c_double(dt), ctypes.c_int32(nsteps))
         return F
 
+    def step_radial_implicit(self, F, dt, nsteps=1):
+        """Split steps in place on F: RK4 on the angular and collision terms, then
+        a backward-Euler radial step (no radial step limit)."""
+        self._call(self.lib.sp6_step_radial_implicit, _ptr(F, "F", self.shape), ctypes.c_double(dt),
+                   ctypes.c_int32(nsteps))
+        return F
+
     KERNEL_CLASSES = ("phi", "theta", "radial", "plane", "filter", "thetaphi")
 
     def step_timed(self, F, dt, nsteps=1):

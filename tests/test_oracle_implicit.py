@@ -74,3 +74,26 @@ def test_constant_state_is_kept():
     p = step.Physics(z, z, z, bc=True, scattering=False, radial_implicit=True)
     F = np.full(g.shape, 2.5)
     np.testing.assert_allclose(step.run(F, g, p, 0.1, 5), F, atol=1e-13)
+
+
+@pytest.mark.parametrize("n_r", [9, 33])
+def test_backward_euler_radial_step_has_no_step_limit(n_r):
+    # App. B: the implicit radial solve sets no Courant limit.  With the inflow
+    # value held, the rest of the line evolves by the non-inflow block of B_i,
+    # whose eigenvalues 1 / (1 + dt lambda) lie inside the unit disc for every dt
+    # (lambda: eigenvalues of cos(Theta_i) D_r with the inflow node removed, in
+    # the right half plane); far beyond the explicit limit it damps hard.
+    g = og.make_grid(1, n_r, 2, 4, 8, 16)
+    for dt in (1e-3, 1e-1, 10.0, 1e3):
+        B = ops.radial_implicit_matrices(g, dt)
+        for i, b in enumerate(B):
+            j = 0 if np.cos(g.Theta[i]) > 0 else n_r - 1
+            keep = [k for k in range(n_r) if k != j]
+            rho = np.max(np.abs(np.linalg.eigvals(b[np.ix_(keep, keep)])))
+            assert rho < 1.0, (dt, i, rho)
+            if dt >= 1e3:
+                assert rho < 0.01
+            # the inflow row is the identity
+            e = np.zeros(n_r)
+            e[j] = 1.0
+            np.testing.assert_allclose(b[j], e, rtol=0, atol=1e-13)
