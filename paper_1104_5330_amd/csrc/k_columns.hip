@@ -170,7 +170,7 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
   const int n_r = d.n_r;
   const uint32_t boff = (uint32_t(lk) * uint32_t(M) + uint32_t(lr)) * 8u;
   auto ld = [&](const double* row) {
-    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(row) + boff);
+    return ld_stream<NT_RAD_LD>(reinterpret_cast<const double*>(reinterpret_cast<const char*>(row) + boff));
   };
   auto at = [&](double* row) { return reinterpret_cast<double*>(reinterpret_cast<char*>(row) + boff); };
   // every extent is a power of two: divisions become shifts
@@ -229,9 +229,9 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
           const double val = cT * acc[rt][v];
           double* dst = at(Tg + int64_t(16 * rt + 4 * v) * M);
           if constexpr (ACCUM)
-            *dst = tv[rt * 4 + v] + val;
+            st_stream<NT_RAD_ST>(dst, tv[rt * 4 + v] + val);
           else
-            *dst = val;
+            st_stream<NT_RAD_ST>(dst, val);
         }
       }
   }
@@ -488,7 +488,7 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 #pragma unroll
     for (int i = 0; i < C::EPT; ++i) {
       const int e = tid + i * C::NTHR;
-      v[i] = e < C::NE ? Y[slab + int64_t(e / CW) * plane + c] : TI(0);
+      v[i] = e < C::NE ? ld_stream<NT_SPH_LD>(Y + (slab + int64_t(e / CW) * plane + c)) : TI(0);
     }
 #pragma unroll
     for (int i = 0; i < C::EPT; ++i) {
@@ -535,7 +535,7 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
   if (isPhi) {
     const int64_t o = slab + int64_t(w) * NPH * plane + c;
 #pragma unroll
-    for (int k = 0; k < NPH; ++k) T[o + int64_t(k) * plane] = z[k] + sY[(w * NPH + k) * CW + col];
+    for (int k = 0; k < NPH; ++k) st_stream<NT_SPH_ST>(T + (o + int64_t(k) * plane), TC(z[k] + sY[(w * NPH + k) * CW + col]));
   }
 }
 

@@ -235,20 +235,20 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
 #pragma unroll
       for (int q = 0; q < C::PPT; ++q) {
         const uint32_t p = uint32_t(tid + q * C::NTHR);
-        yi[q] = Yb[p];
-        ti[q] = needT ? Tb[p] : TO(0);
-        if constexpr (NA && NY) ai[q] = Ab[p];
-        if constexpr (NY) yo[q] = Xb[p];
+        yi[q] = ld_stream<NT_PLANE_LD>(Yb + p);
+        ti[q] = needT ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
+        if constexpr (NA && NY) ai[q] = ld_stream<NT_PLANE_LD>(Ab + p);
+        if constexpr (NY) yo[q] = ld_stream<NT_PLANE_LD>(Xb + p);
       }
     } else {
 #pragma unroll
       for (int q = 0; q < C::PPT; ++q) {
         const uint32_t p = uint32_t(tid + q * C::NTHR);
         const bool ok = plane0 + int(p) / C::PLANE < npl;
-        yi[q] = ok ? Yb[p] : TY(0);
-        ti[q] = (ok && needT) ? Tb[p] : TO(0);
-        if constexpr (NA && NY) ai[q] = ok ? Ab[p] : 0.0;
-        if constexpr (NY) yo[q] = ok ? Xb[p] : 0.0;
+        yi[q] = ok ? ld_stream<NT_PLANE_LD>(Yb + p) : TY(0);
+        ti[q] = (ok && needT) ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
+        if constexpr (NA && NY) ai[q] = ok ? ld_stream<NT_PLANE_LD>(Ab + p) : 0.0;
+        if constexpr (NY) yo[q] = ok ? ld_stream<NT_PLANE_LD>(Xb + p) : 0.0;
       }
     }
   };
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
 #pragma unroll
       for (int q = 0; q < C::PPT; ++q) {
         const uint32_t p = uint32_t(tid + q * C::NTHR);
-        av[q] = plane0 + int(p) / C::PLANE < npl ? Ab[p] : 0.0;
+        av[q] = plane0 + int(p) / C::PLANE < npl ? ld_stream<NT_PLANE_LD>(Ab + p) : 0.0;
       }
     }
     if (grp + 1 < gend) {
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
       if (useTh) LY += double(sR[0][lp]);
       if (usePh) LY += double(sR[1][lp]);
       if (a.mode == PM_APPLY) {
-        a.out[gp] = LY;
+        st_stream<NT_PLANE_ST>(a.out + gp, LY);
         continue;
       }
       const int iTh = (p % C::PLANE) / C::NF;
@@ -419,14 +419,14 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
       double k = -LY + pi.eta - (pi.kappa + pi.sigma) * Yv + pi.sigma * inscat;
       if (d.bc && ((pi.j == 0 && sCT[iTh] > 0.0) || (pi.j == d.n_r - 1 && sCT[iTh] < 0.0))) k = 0.0;
       if (a.mode == PM_RHS) {
-        a.out[gp] = k;
+        st_stream<NT_PLANE_ST>(a.out + gp, k);
         continue;
       }
       double ab = Yv, yb = Yv;
       if constexpr (NA) ab = av[q];
       if constexpr (NY) yb = yv[q];
-      if (a.accdst) a.accdst[gp] = ab + a.cb * k;
-      if (ynext) ynext[gp] = TO(yb + a.cn * k);
+      if (a.accdst) st_stream<NT_PLANE_ST>(a.accdst + gp, ab + a.cb * k);
+      if (ynext) st_stream<NT_PLANE_ST>(ynext + gp, TO(yb + a.cn * k));
     }
     __syncthreads();
   }
