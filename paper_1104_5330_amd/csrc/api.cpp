@@ -101,6 +101,13 @@ hipError_t upload(sp6_grid g, const std::vector<T>& v, const T** out) {
 
 size_t state_bytes(const sp6_grid g) { return size_t(g->d.P) * sizeof(double); }
 
+// sizes for the next theta-phi, radial or plane pass, with the traversal
+// direction flipped from the previous such pass
+const KDims& next_pass(sp6_grid g) {
+  g->d.rev ^= 1;
+  return g->d;
+}
+
 sp6_status check_grid(sp6_grid g) {
   if (!g) return fail(SP6_ERR_ARG, "grid handle is NULL");
   return SP6_OK;
@@ -176,7 +183,7 @@ hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transp
   bool acc = false;
   const double sg = transpose ? -1.0 : 1.0;
   if ((terms & 6u) == 6u && sphere_fusable(g->d, false)) {
-    e = launch_sphere(g->d, g->t, Y, g->T, sg, mask_in, in_scale, g->stream);
+    e = launch_sphere(next_pass(g), g->t, Y, g->T, sg, mask_in, in_scale, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
     if (e != hipSuccess) return e;
     acc = true;
@@ -195,7 +202,7 @@ hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transp
     acc = true;
   }
   if (terms & 1u) {
-    e = launch_radial(g->d, g->t, Y, g->T, acc, transpose, mask_in, in_scale, g->stream);
+    e = launch_radial(next_pass(g), g->t, Y, g->T, acc, transpose, mask_in, in_scale, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_RADIAL);
     if (e != hipSuccess) return e;
     acc = true;
@@ -210,7 +217,7 @@ hipError_t column_terms_mixed(sp6_grid g, const void* Y, bool y_f32, uint32_t te
   hipError_t e = hipSuccess;
   bool acc = false;
   if ((terms & 6u) == 6u && sphere_fusable(g->d, true)) {
-    e = launch_sphere_mixed(g->d, g->t, Y, y_f32, g->Tf, g->stream);
+    e = launch_sphere_mixed(next_pass(g), g->t, Y, y_f32, g->Tf, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
     if (e != hipSuccess) return e;
     acc = true;
@@ -229,7 +236,7 @@ hipError_t column_terms_mixed(sp6_grid g, const void* Y, bool y_f32, uint32_t te
     acc = true;
   }
   if (terms & 1u) {
-    e = launch_radial_bf16x3(g->d, g->t, Y, y_f32, g->Tf, acc, g->stream);
+    e = launch_radial_bf16x3(next_pass(g), g->t, Y, y_f32, g->Tf, acc, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_RADIAL);
     if (e != hipSuccess) return e;
     acc = true;
@@ -262,7 +269,7 @@ sp6_status fp64_rhs_like(sp6_grid g, const double* F, double* out, int mode, uin
   a.T = wrote ? (mixed ? static_cast<const void*>(g->Tf) : static_cast<const void*>(g->T)) : nullptr;
   a.out = out;
   a.terms = terms;
-  HIP_TRY(launch_plane(g->d, g->t, g->c, a, g->stream), "plane pass");
+  HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
   return SP6_OK;
 }
 
@@ -648,7 +655,7 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
           a.ysrc = nullptr, a.ynext = nullptr, a.cn = 0.0;
           break;
       }
-      HIP_TRY(launch_plane(d, g->t, g->c, a, g->stream), "plane pass");
+      HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
       if (tm) HIP_TRY(tm->mark(g->stream, KC_PLANE), "event");
     }
     if (radial_implicit) {
@@ -705,7 +712,7 @@ sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nst
       a.accsrc = H, a.cb = dt;
       a.ysrc = H, a.cn = 1.5 * dt;
     }
-    HIP_TRY(launch_plane(d, g->t, g->c, a, g->stream), "plane pass");
+    HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
     if (g->desc.filter) {
       HIP_TRY(launch_filter(d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
       HIP_TRY(launch_filter(d, g->t, H, g->desc.filter == 2 ? 1 : 0, g->stream), "filter of H");
@@ -776,7 +783,7 @@ sp6_status sp6_adjoint_step(sp6_grid g, const double* Fn, double dt, double* lam
     a.ysrc = (s == 1) ? nullptr : Fn;
     a.ynext = Ys[s + 1];
     a.cn = cn[s];
-    HIP_TRY(launch_plane(d, g->t, g->c, a, g->stream), "plane pass");
+    HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
   }
   // transposed stages 4, 3, 2, 1
   for (int s = 4; s >= 1; --s) {

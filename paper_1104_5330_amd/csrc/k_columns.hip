@@ -157,15 +157,15 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
 #pragma unroll
     for (int s = 0; s < KS; ++s) a[rt][s] = Dp[(16 * rt + lr) * t.KP + 4 * s + lk];
 
-  // column groups of 16; each workgroup walks one contiguous range of them, its
-  // wavefronts side by side.  Addresses are a wave-uniform row pointer plus the
-  // 32-bit per-lane byte offset of row lk, column lr.  Only the last k-step and
-  // the last row tile can reach past n_r (KS = ceil(n_r / 4)); every other load
-  // and store is unconditional.
+  // column groups of 16; the resident workgroups advance through them together
+  // (round k takes groups k G .. k G + G - 1, G = gridDim NWV, the wavefronts of a
+  // workgroup side by side), in the direction d.rev.  Addresses are a
+  // wave-uniform row pointer plus the 32-bit per-lane byte offset of row lk,
+  // column lr.  Only the last k-step and the last row tile can reach past n_r
+  // (KS = ceil(n_r / 4)); every other load and store is unconditional.
   const int gpe = int(d.M / 16);
   const int ngroups = gpe * d.n_eps;
-  const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
-  const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
+  const int gstride = int(gridDim.x) * NWV;
   const int64_t M = d.M;
   const int n_r = d.n_r;
   const uint32_t boff = (uint32_t(lk) * uint32_t(M) + uint32_t(lr)) * 8u;
@@ -175,7 +175,8 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
   auto at = [&](double* row) { return reinterpret_cast<double*>(reinterpret_cast<char*>(row) + boff); };
   // every extent is a power of two: divisions become shifts
   const int sh_g = __builtin_ctz(gpe), sh_P = __builtin_ctz(d.n_Ph);
-  for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
+  for (int k = int(blockIdx.x) * NWV + wave; k < ngroups; k += gstride) {
+    const int g = d.rev ? ngroups - 1 - k : k;
     const int e = g >> sh_g;
     const int c0 = (g & (gpe - 1)) * 16;
     const int64_t gb = int64_t(e) * n_r * M + c0;
@@ -459,7 +460,9 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
   // blocks b, b + 8, ..., b + 8 (G - 1) run on the same XCD; they take the G
   // consecutive tiles whose column runs (R = CW / 2 values) share 128-byte lines
   constexpr int G = sphere_group<CW, TI>();
-  const int b = int(blockIdx.x);
+  // (descending: block b takes the place of block gridDim - 1 - b; the grid is a
+  // multiple of 8 G, so the XCD pairing is kept)
+  const int b = d.rev ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
   const int tile = (b / (8 * G)) * (8 * G) + (b % 8) * G + (b / 8) % G;
   if (tile >= ntiles) return;
   const int tpp = d.plane / CW;

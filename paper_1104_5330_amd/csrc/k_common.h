@@ -53,7 +53,7 @@ SP6_DEV int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 // pass; on the radial pass it gains 2 % there and loses as much in the plane
 // pass; on the theta-phi pass (partial-line stores) it costs 12 %.
 #ifndef SP6_NT
-#define SP6_NT 3
+#define SP6_NT 195
 #endif
 template <int BIT, typename T>
 SP6_DEV T ld_stream(const T* p) {
@@ -69,7 +69,12 @@ SP6_DEV void st_stream(T* p, T v) {
   else
     *p = v;
 }
-enum { NT_PLANE_LD = 1, NT_PLANE_ST = 2, NT_RAD_LD = 4, NT_RAD_ST = 8, NT_SPH_LD = 16, NT_SPH_ST = 32 };
+// plane pass: 1 stage input and T loads, 2 next-stage state (or output) stores,
+// 64 accumulator and y loads, 128 accumulator stores
+enum {
+  NT_PLANE_LD = 1, NT_PLANE_ST = 2, NT_RAD_LD = 4, NT_RAD_ST = 8, NT_SPH_LD = 16, NT_SPH_ST = 32,
+  NT_PLANE_LDA = 64, NT_PLANE_STA = 128
+};
 
 // Line-operator tables in constant memory.  The Fourier derivative and the
 // filter on an L-point periodic line depend on L only, so one copy per L serves

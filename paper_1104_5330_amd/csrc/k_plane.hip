@@ -215,13 +215,15 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
   const TO* Tin = static_cast<const TO*>(a.T);
   TO* ynext = static_cast<TO*>(a.ynext);
 
-  // each workgroup walks one contiguous range of plane groups; every global
-  // operand of the next group (state, T, acc, y, and the per-plane coefficients)
-  // is loaded one iteration ahead (register double buffering), so its loads are
-  // in flight during the lines and the epilogue.  Groups that lie wholly inside
-  // the array (all but possibly the last) load without per-lane predicates.
-  const int per_blk = (ngroups + gridDim.x - 1) / gridDim.x;
-  const int gbeg = per_blk * blockIdx.x, gend = min(ngroups, gbeg + per_blk);
+  // the resident workgroups advance through the plane groups together (round k
+  // takes groups k gridDim .. k gridDim + gridDim - 1), in the direction d.rev;
+  // every global operand of a workgroup's next group (state, T, acc, y, and the
+  // per-plane coefficients) is loaded one iteration ahead (register double
+  // buffering), so its loads are in flight during the lines and the epilogue.
+  // Groups that lie wholly inside the array (all but possibly the last) load
+  // without per-lane predicates.
+  const int gstep = int(gridDim.x);
+  auto gid = [&](int k) { return d.rev ? ngroups - 1 - k : k; };
   const bool apply = a.mode == PM_APPLY, scat = !apply && d.scattering;
   const int sh_ph = __builtin_ctz(d.n_ph), sh_th = __builtin_ctz(d.n_th);
   auto load_group = [&](int g, TY* yi, TO* ti, double* ai, double* yo) {
@@ -237,8 +239,8 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
         const uint32_t p = uint32_t(tid + q * C::NTHR);
         yi[q] = ld_stream<NT_PLANE_LD>(Yb + p);
         ti[q] = needT ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && NY) ai[q] = ld_stream<NT_PLANE_LD>(Ab + p);
-        if constexpr (NY) yo[q] = ld_stream<NT_PLANE_LD>(Xb + p);
+        if constexpr (NA && NY) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
+        if constexpr (NY) yo[q] = ld_stream<NT_PLANE_LDA>(Xb + p);
       }
     } else {
 #pragma unroll
@@ -247,8 +249,8 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
         const bool ok = plane0 + int(p) / C::PLANE < npl;
         yi[q] = ok ? ld_stream<NT_PLANE_LD>(Yb + p) : TY(0);
         ti[q] = (ok && needT) ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && NY) ai[q] = ok ? ld_stream<NT_PLANE_LD>(Ab + p) : 0.0;
-        if constexpr (NY) yo[q] = ok ? ld_stream<NT_PLANE_LD>(Xb + p) : 0.0;
+        if constexpr (NA && NY) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
+        if constexpr (NY) yo[q] = ok ? ld_stream<NT_PLANE_LDA>(Xb + p) : 0.0;
       }
     }
   };
@@ -272,12 +274,13 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
   TO tn[C::PPT];
   double an[NA_AHEAD ? C::PPT : 1], yn[NY ? C::PPT : 1];
   PlaneCoef pin{};
-  int grp = gbeg;
-  if (grp < gend) {
-    load_group(grp, yin, tn, an, yn);
-    load_info(grp, pin);
+  int kk = int(blockIdx.x);
+  if (kk < ngroups) {
+    load_group(gid(kk), yin, tn, an, yn);
+    load_info(gid(kk), pin);
   }
-  for (; grp < gend; ++grp) {
+  for (; kk < ngroups; kk += gstep) {
+    const int grp = gid(kk);
     const int plane0 = grp * C::NPW;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) sY[C::lds(tid + q * C::NTHR)] = yin[q];
@@ -310,12 +313,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
 #pragma unroll
       for (int q = 0; q < C::PPT; ++q) {
         const uint32_t p = uint32_t(tid + q * C::NTHR);
-        av[q] = plane0 + int(p) / C::PLANE < npl ? ld_stream<NT_PLANE_LD>(Ab + p) : 0.0;
+        av[q] = plane0 + int(p) / C::PLANE < npl ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
       }
     }
-    if (grp + 1 < gend) {
-      load_group(grp + 1, yin, tn, an, yn);
-      load_info(grp + 1, pin);
+    if (kk + gstep < ngroups) {
+      load_group(gid(kk + gstep), yin, tn, an, yn);
+      load_info(gid(kk + gstep), pin);
     }
 
     {  // line phase
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((N
       double ab = Yv, yb = Yv;
       if constexpr (NA) ab = av[q];
       if constexpr (NY) yb = yv[q];
-      if (a.accdst) st_stream<NT_PLANE_ST>(a.accdst + gp, ab + a.cb * k);
+      if (a.accdst) st_stream<NT_PLANE_STA>(a.accdst + gp, ab + a.cb * k);
       if (ynext) st_stream<NT_PLANE_ST>(ynext + gp, TO(yb + a.cn * k));
     }
     __syncthreads();

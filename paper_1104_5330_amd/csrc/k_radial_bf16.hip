@@ -47,8 +47,9 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
       }
   const int gpe = int(d.M / 16);
   const int ngroups = gpe * d.n_eps;
-  const int per_blk = ((ngroups + int(gridDim.x) - 1) / int(gridDim.x) + NWV - 1) / NWV * NWV;
-  const int gend = min(ngroups, per_blk * (int(blockIdx.x) + 1));
+  // the resident workgroups advance through the groups together, in the
+  // direction d.rev
+  const int gstride = int(gridDim.x) * NWV;
   const int64_t M = d.M;
   const int n_r = d.n_r;
   // wave-uniform row pointers plus 32-bit per-lane byte offsets (B rows 8 lg + q,
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
   auto atT = [&](float* row) { return reinterpret_cast<float*>(reinterpret_cast<char*>(row) + offC); };
   // every extent is a power of two: divisions become shifts
   const int sh_g = __builtin_ctz(gpe), sh_P = __builtin_ctz(d.n_Ph);
-  for (int g = per_blk * int(blockIdx.x) + wave; g < gend; g += NWV) {
+  for (int k = int(blockIdx.x) * NWV + wave; k < ngroups; k += gstride) {
+    const int g = d.rev ? ngroups - 1 - k : k;
     const int e = g >> sh_g;
     const int c0 = (g & (gpe - 1)) * 16;
     const float cT = float(t.cos_Th[((c0 + lr) >> sh_P) & (d.n_Th - 1)]);

@@ -23,6 +23,11 @@ struct KDims {
   int64_t nplanes;  // n_eps * n_r * n_th * n_ph
   int bc, scattering;
   int ncu;          // compute units of the device (persistent grids)
+  // traversal direction of the pass passes (fused theta-phi, radial, plane):
+  // 0 ascending addresses, 1 descending.  The host alternates it from one pass
+  // to the next, so that a pass first reads what the previous one touched last
+  // (still in the last-level cache).  Results do not depend on it.
+  int rev;
 };
 
 struct KTab {
