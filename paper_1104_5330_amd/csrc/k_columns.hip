@@ -172,6 +172,9 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
   auto ld = [&](const double* row) {
     return ld_stream<NT_RAD_LD>(reinterpret_cast<const double*>(reinterpret_cast<const char*>(row) + boff));
   };
+  auto ldT = [&](const double* row) {
+    return ld_stream<NT_RAD_LDT>(reinterpret_cast<const double*>(reinterpret_cast<const char*>(row) + boff));
+  };
   auto at = [&](double* row) { return reinterpret_cast<double*>(reinterpret_cast<char*>(row) + boff); };
   // every extent is a power of two: divisions become shifts
   const int sh_g = __builtin_ctz(gpe), sh_P = __builtin_ctz(d.n_Ph);
@@ -201,9 +204,9 @@ __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __
         for (int v = 0; v < 4; ++v) {
           const double* row = Tg + int64_t(16 * rt + 4 * v) * M;
           if (rt < NRT - 1)
-            tv[rt * 4 + v] = ld(row);
+            tv[rt * 4 + v] = ldT(row);
           else
-            tv[rt * 4 + v] = 16 * rt + lk + 4 * v < n_r ? ld(row) : 0.0;
+            tv[rt * 4 + v] = 16 * rt + lk + 4 * v < n_r ? ldT(row) : 0.0;
         }
     }
     if (mask_in) {

@@ -45,15 +45,15 @@ SP6_DEV void eo_pairs(const TT* __restrict__ tab, int i0, const T (&v)[L], Emit&
 
 SP6_DEV int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// Streaming access: data read or written once per pass.  SP6_NT selects, per
-// kernel family, loads (bit 2k) and stores (bit 2k + 1) with the nontemporal
-// hint (k = 0 plane pass, 1 radial pass, 2 fused theta-phi pass).  Measured on
-// the 33 x 16 x 32 x 16 x 32 grid: the hint on both the loads and the stores of
-// the plane pass takes it from 4.66 to 5.03 TB/s and speeds up the next theta-phi
-// pass; on the radial pass it gains 2 % there and loses as much in the plane
-// pass; on the theta-phi pass (partial-line stores) it costs 12 %.
+// Streaming access: data read or written once per pass.  SP6_NT selects which
+// global accesses carry the nontemporal hint (bits below).  Measured on the
+// 33 x 16 x 32 x 16 x 32 grid: on the loads and stores of the plane pass it takes
+// the pass from 4.66 to 5.03 TB/s; on the radial pass's T loads and stores from
+// 4.84 to 5.0 TB/s (its stage-input loads keep the plain hint: that input is read
+// again by the plane pass, which finds it in the last-level cache); on the
+// theta-phi pass (partial-line stores) it costs 12 %, so that pass has none.
 #ifndef SP6_NT
-#define SP6_NT 195
+#define SP6_NT 459
 #endif
 template <int BIT, typename T>
 SP6_DEV T ld_stream(const T* p) {
@@ -70,10 +70,11 @@ SP6_DEV void st_stream(T* p, T v) {
     *p = v;
 }
 // plane pass: 1 stage input and T loads, 2 next-stage state (or output) stores,
-// 64 accumulator and y loads, 128 accumulator stores
+// 64 accumulator and y loads, 128 accumulator stores; radial pass: 4 stage input
+// loads, 256 T loads, 8 T stores
 enum {
   NT_PLANE_LD = 1, NT_PLANE_ST = 2, NT_RAD_LD = 4, NT_RAD_ST = 8, NT_SPH_LD = 16, NT_SPH_ST = 32,
-  NT_PLANE_LDA = 64, NT_PLANE_STA = 128
+  NT_PLANE_LDA = 64, NT_PLANE_STA = 128, NT_RAD_LDT = 256
 };
 
 // Line-operator tables in constant memory.  The Fourier derivative and the
