@@ -183,8 +183,14 @@ struct PlaneInfo {
 // input, TC: type of the line derivatives.  The collision term, the inflow mask
 // and the RK update are FP64 in every instantiation.
 // AN: anisotropic scattering (plane moments instead of the angular mean).
+// FP64 stages that read the accumulator (2, 3 and 4) on 16 x 32 planes: capped at
+// 128 VGPRs for four waves per SIMD (measured 536 -> 528 us for the pass; stages
+// 2 and 3 then spill a few registers)
+constexpr int plane_waves_per_eu(int nt, bool na, bool an, int tc_bytes) {
+  return (na && !an && tc_bytes == 8 && nt == 16) ? 4 : 1;
+}
 template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC, bool AN>
-__global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu((NA && !NY && !AN && sizeof(TC) == 8 && NT == 16) ? 4 : 1))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
+__global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
   __shared__ TY sY[C::PTSP];
   __shared__ TC sR[2][C::PTSP];
