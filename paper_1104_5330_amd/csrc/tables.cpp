@@ -117,6 +117,12 @@ std::string validate_desc(const sp6_desc& d, sp6_status* code) {
     std::snprintf(buf, sizeof buf, "grid of %.3g points is above the supported maximum 4e10", P);
     return buf;
   }
+  // plane, column-group and tile counts are 32-bit in the kernels
+  const double planes = double(d.n_eps) * d.n_r * d.n_theta * d.n_phi;
+  if (planes > 2147483647.0) {
+    std::snprintf(buf, sizeof buf, "%.3g (Theta, Phi) planes is above the supported maximum 2^31 - 1", planes);
+    return buf;
+  }
   *code = SP6_ERR_ARG;
   if (!(d.r_in > 0.0) || !(d.r_out > d.r_in) || !std::isfinite(d.r_out)) return "need 0 < r_in < r_out";
   if (d.precision != SP6_FP64 && d.precision != SP6_MIXED) return "precision must be SP6_FP64 or SP6_MIXED";

@@ -76,6 +76,10 @@ def test_validate_null_and_max_size(lib):
     big = desc(n_eps=100000, n_r=80, n_theta=32, n_phi=64, n_Theta=32, n_Phi=64)
     assert lib.sp6_validate_desc(ctypes.byref(big)) == _lib.SP6_ERR_SHAPE
     assert "maximum" in lib.sp6_last_error().decode()
+    # under the point limit but with more planes than 32-bit kernel counters take
+    many = desc(n_eps=1_900_000, n_r=80, n_theta=4, n_phi=8, n_Theta=2, n_Phi=4)
+    assert lib.sp6_validate_desc(ctypes.byref(many)) == _lib.SP6_ERR_SHAPE
+    assert "planes" in lib.sp6_last_error().decode()
 
 
 def test_null_handle_calls_fail_cleanly(lib):
