@@ -601,7 +601,7 @@ template <int KS, bool ACCUM>
 void launch_radial_t(const KDims& d, const KTab& t, const double* Y, double* T, bool transpose, bool mask_in,
                      double in_scale, hipStream_t s) {
   const int64_t ngroups = (d.M / 16) * d.n_eps;
-  // one resident round of workgroups: every workgroup walks an equal contiguous range
+  // one resident round of workgroups, advancing through the column groups together
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_radial<KS, ACCUM>, CB, 0) != hipSuccess || per_cu < 1)
     per_cu = 1;

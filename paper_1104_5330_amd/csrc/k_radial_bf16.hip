@@ -138,7 +138,7 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
 template <int NRT, typename TI>
 void launch_t(const KDims& d, const KTab& t, const void* Y, float* T, bool accum, hipStream_t s) {
   const int64_t ngroups = (d.M / 16) * d.n_eps;
-  // one resident round of workgroups: every workgroup walks an equal contiguous range
+  // one resident round of workgroups, advancing through the column groups together
   auto blocks_for = [&](auto kernel) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, CB, 0) != hipSuccess || per_cu < 1) per_cu = 1;
