@@ -97,3 +97,28 @@ def test_backward_euler_radial_step_has_no_step_limit(n_r):
             e = np.zeros(n_r)
             e[j] = 1.0
             np.testing.assert_allclose(b[j], e, rtol=0, atol=1e-13)
+
+
+def test_backward_euler_front_speed_app_b():
+    # App. B's 1D experiment: a step profile entering the shell at r_in with
+    # speed C (here C = cos Theta_0), 65 Chebyshev points, dt = 8 (R2 - R1) /
+    # (C N_r^2) (the paper's Delta t_opt).  The paper reports the right
+    # propagation speed: the half-height point sits at r_in + C t.
+    n_r = 65
+    g = og.make_grid(1, n_r, 2, 4, 8, 16)
+    C = np.cos(g.Theta[0])
+    dt = 8.0 * (g.r_out - g.r_in) / (C * n_r ** 2)
+    B = ops.radial_implicit_matrices(g, dt)[0]
+    u = np.zeros(n_r)
+    u[0] = 1.0
+    nsteps = int(round(1.0 / dt))
+    for _ in range(nsteps):
+        u = B @ u
+    t = nsteps * dt
+    x = np.linspace(g.r_in, g.r_out, 2001)
+    prof = np.polynomial.chebyshev.Chebyshev.fit(g.r, u, n_r - 1, domain=[g.r_in, g.r_out])(x)
+    front = x[np.argmax(prof < 0.5)]
+    assert abs(front - (g.r_in + C * t)) < 0.05
+    # the profile stays bounded (no growth) and is 1 behind the front
+    assert np.max(np.abs(u)) < 1.3
+    assert abs(u[0] - 1.0) < 1e-12  # the inflow value is held (up to the rounding of the inverse)
