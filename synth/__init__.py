@@ -7,5 +7,5 @@ quadratures, no time stepping), so it can feed both the oracle and the GPU
 path without either depending on the other.
 """
 
-from .configs import CONFIGS, Config, config  # noqa: F401
+from .configs import WORKLOADS, Config, config  # noqa: F401
 from . import fields  # noqa: F401

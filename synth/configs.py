@@ -68,7 +68,7 @@ class Config:
         return replace(self, **kw)
 
 
-CONFIGS = {
+WORKLOADS = {
     1: Config("vacuum_17x8x16x8x16", 1, 17, 8, 16, 8, 16, 10, "vacuum"),
     2: Config("emit_abs_33x16x32x16x32_g8", 8, 33, 16, 32, 16, 32, 100, "emit_abs"),
     3: Config("scatter_33x16x32x16x32_g8", 8, 33, 16, 32, 16, 32, 100, "scatter"),
@@ -80,4 +80,4 @@ CONFIGS = {
 
 
 def config(n):
-    return CONFIGS[n]
+    return WORKLOADS[n]
