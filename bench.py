@@ -9,6 +9,7 @@ resident in HBM.  Inputs are synthetic and seeded (no dataset is involved).
 Also measured on the same JSON line ("forms"):
   mixed   : the scattering workload (same grid, sigma = kappa/2) on the mixed path,
             with its error against the FP64 path after the timed steps;
+  large   : the 1.09e9-point scattering workload, FP64 and mixed;
   implicit: the headline workload with the split step of App. B (backward-Euler
             radial solve after RK4 on the other terms);
   adjoint : the 4-group workload (same angular grid), 200 steps forward plus the
@@ -59,7 +60,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["all", "fp64", "mixed", "thomson", "shell", "ab2", "implicit", "adjoint"], default="all")
+    ap.add_argument("--form", choices=["all", "fp64", "mixed", "large", "thomson", "shell", "ab2", "implicit", "adjoint"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -154,6 +155,33 @@ def form_mixed(args):
         "error_vs_fp64": {"max_rel": err_max, "l2_rel": err_l2, "after_steps": args.steps},
         "hbm_fraction_algorithmic_104B": P * args.steps / (ms / 1e3) * FUSED_MIN_B["mixed"] / (HBM_PEAK_GBS * 1e9),
         "kernels": kernel_table(kt, P, BYTES_MIXED, ms),
+    }
+
+
+def form_large(args):
+    """The large scattering workload (4 groups, (65, 32, 64, 32, 64): 1.09e9 points,
+    8.7 GB per FP64 array), FP64 and mixed, a few steps each: theta lines of 64
+    points (separate theta and phi passes), 2048-point planes."""
+    import torch
+    import synth
+    cfg = synth.config(5)
+    steps = max(1, min(args.steps, 10))
+    Fm, F0, ms_m, kt_m = run_steps(cfg, "mixed", True, steps, 1)
+    F64, _, ms, kt = run_steps(cfg, "fp64", True, steps, 1, F0=F0)
+    del F0
+    err_max = ((Fm - F64).abs().max() / F64.abs().max()).item()
+    err_l2 = (torch.linalg.vector_norm(Fm - F64) / torch.linalg.vector_norm(F64)).item()
+    P = cfg.points
+    # the separate theta pass reads Y and T and writes T (24 B), the phi pass 16 B
+    return {
+        "workload": cfg.name, "grid": list(cfg.shape), "points": P, "steps": steps,
+        "physics": "emission+absorption+isotropic scattering",
+        "fp64": {"value": P * steps / (ms / 1e3), "ms_per_step": ms / steps,
+                 "kernels": kernel_table(kt, P, BYTES_FP64, ms)},
+        "mixed": {"value": P * steps / (ms_m / 1e3), "ms_per_step": ms_m / steps,
+                  "kernels": kernel_table(kt_m, P, BYTES_MIXED, ms_m),
+                  "error_vs_fp64": {"max_rel": err_max, "l2_rel": err_l2, "after_steps": steps}},
+        "unit": "grid-point updates/s",
     }
 
 
@@ -395,6 +423,8 @@ def main():
         forms["fp64"] = {"value": value, "ms_per_step": ms / args.steps}
     if args.form in ("all", "mixed"):
         forms["mixed"] = form_mixed(args)
+    if args.form in ("all", "large"):
+        forms["large"] = form_large(args)
     if args.form in ("all", "thomson"):
         forms["thomson"] = form_thomson(args)
     if args.form in ("all", "shell"):

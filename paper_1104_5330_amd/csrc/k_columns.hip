@@ -459,7 +459,7 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
                                                                    int mask_in, double in_scale, int ntiles) {
   using C = SPC<NTH, CW, TC>;
   constexpr int L = C::L, NPH = C::NPH;
-  __shared__ TC sY[C::NE];
+  __shared__ __align__(16) TC sY[C::NE];
   // blocks b, b + 8, ..., b + 8 (G - 1) run on the same XCD; they take the G
   // consecutive tiles whose column runs (R = CW / 2 values) share 128-byte lines
   constexpr int G = sphere_group<CW, TI>();
@@ -485,7 +485,30 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
   const int plane = d.plane;
   const int tid = int(threadIdx.x);
 
-  {  // stage the tile: element e = combo * CW + col, combo = theta * n_phi + phi
+  // stage the tile: element e = combo * CW + col, combo = theta * n_phi + phi
+  constexpr bool PAIRS = sizeof(TI) == 8 && sizeof(TC) == 8 && CW % 2 == 0 && C::NE % (2 * C::NTHR) == 0 &&
+                         C::NTHR % (CW / 2) == 0;
+  if constexpr (PAIRS) {
+    // 16-byte loads of two neighbouring columns of one run (runs have an even
+    // length R >= 2 and start at even columns, so the pair is contiguous and
+    // 16-byte aligned in an aligned state)
+    constexpr int PPT = C::NE / (2 * C::NTHR);
+    const int q = tid % (CW / 2);
+    const int c = colc(2 * q);
+    TC s_in = TC(in_scale);
+    if (mask_in && is_inflow(d, t, j, c / d.n_Ph)) s_in = TC(0);
+    double2 v[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int p = tid + i * C::NTHR;  // pair p = combo * CW / 2 + q
+      v[i] = *reinterpret_cast<const double2*>(Y + (slab + int64_t(p / (CW / 2)) * plane + c));
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int p = tid + i * C::NTHR;
+      reinterpret_cast<double2*>(sY)[p] = double2{v[i].x * s_in, v[i].y * s_in};
+    }
+  } else {
     const int col = tid % CW;
     const int c = colc(col);
     TC s_in = TC(in_scale);

@@ -32,7 +32,9 @@ struct PC {
   static constexpr int PLANE = NT * NF;
   static constexpr int LPP = 2 * NT;      // lines per plane
   static constexpr int NPW = 64 / LPP;    // planes per workgroup
-  static constexpr int NW = NT >= 4 ? 4 : NT;  // wavefronts; each computes PPW output pairs
+  // wavefronts, each computing PPW output pairs of every line (eight for the
+  // 2048-point planes: half the registers per thread of four)
+  static constexpr int NW = NT >= 32 ? 8 : (NT >= 4 ? 4 : NT);
   static constexpr int PPW = NT / NW;
   static constexpr int PTS = NPW * PLANE;  // points per workgroup (64 NT)
   static constexpr int NTHR = 64 * NW;
@@ -185,8 +187,10 @@ struct PlaneInfo {
 // AN: anisotropic scattering (plane moments instead of the angular mean).
 // FP64 stages that read the accumulator (2, 3 and 4) on 16 x 32 planes: capped at
 // 128 VGPRs for four waves per SIMD (measured 536 -> 528 us for the pass; stages
-// 2 and 3 then spill a few registers)
+// 2 and 3 then spill a few registers).  2048-point planes (eight wavefronts per
+// workgroup): 128 VGPRs, so that two workgroups share a CU.
 constexpr int plane_waves_per_eu(int nt, bool na, bool an, int tc_bytes) {
+  if (nt == 32) return 4;
   return (na && !an && tc_bytes == 8 && nt == 16) ? 4 : 1;
 }
 template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC, bool AN>
