@@ -193,6 +193,19 @@ sp6_status sp6_step_timed(sp6_grid grid, double* F, double dt, int32_t nsteps, d
 sp6_status sp6_adjoint_step(sp6_grid grid, const double* F_n, double dt, double* lam,
                             double* grad_kappa, double* grad_eta, double* grad_sigma);
 
+/* One sp6_step(F, dt, 1) that also keeps its stage inputs: Ystages (device,
+ * 3 state arrays back to back, caller-owned, distinct from F) receives Y2, Y3,
+ * Y4 = F_n + (dt/2) k1, F_n + (dt/2) k2, F_n + dt k3.  F is advanced exactly as by
+ * sp6_step.  FP64 handles only.  For sp6_adjoint_step_stages. */
+sp6_status sp6_step_stages(sp6_grid grid, double* F, double dt, double* Ystages);
+
+/* sp6_adjoint_step with the stage inputs of the step read from Ystages (as
+ * written by sp6_step_stages from the same F_n, dt and coefficients) instead of
+ * recomputed: three fewer stage evaluations.  Same results as
+ * sp6_adjoint_step. */
+sp6_status sp6_adjoint_step_stages(sp6_grid grid, const double* F_n, const double* Ystages, double dt, double* lam,
+                                   double* grad_kappa, double* grad_eta, double* grad_sigma);
+
 /* Apply the spectral filter once, in place: the angular line filters, and the
  * radial one when desc.filter = 2 (desc.filter = 0 still applies the angular
  * filters). */

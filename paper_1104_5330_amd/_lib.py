@@ -19,7 +19,7 @@ SYMBOLS = [
     "sp6_validate_desc", "sp6_create", "sp6_destroy", "sp6_set_stream", "sp6_last_error",
     "sp6_get_nodes", "sp6_get_weights", "sp6_set_coefficients", "sp6_set_scattering_kernel", "sp6_set_inflow",
     "sp6_project_inflow", "sp6_apply_L", "sp6_apply_L_terms", "sp6_apply_LT", "sp6_rhs",
-    "sp6_step", "sp6_step_radial_implicit", "sp6_step_ab2", "sp6_step_timed", "sp6_adjoint_step", "sp6_apply_filter", "sp6_diagnostics",
+    "sp6_step", "sp6_step_stages", "sp6_adjoint_step_stages", "sp6_step_radial_implicit", "sp6_step_ab2", "sp6_step_timed", "sp6_adjoint_step", "sp6_apply_filter", "sp6_diagnostics",
     "sp6_outgoing_flux", "sp6_outgoing_flux_T", "sp6_device_bytes",
 ]
 
@@ -72,6 +72,8 @@ def load():
         "sp6_apply_LT": (S, [P, P, P]),
         "sp6_rhs": (S, [P, P, P]),
         "sp6_step": (S, [P, P, D, I32]),
+        "sp6_step_stages": (S, [P, P, D, P]),
+        "sp6_adjoint_step_stages": (S, [P, P, P, D, P, P, P, P]),
         "sp6_step_radial_implicit": (S, [P, P, D, I32]),
         "sp6_step_ab2": (S, [P, P, P, D, I32, I32]),
         "sp6_step_timed": (S, [P, P, D, I32, dp, ctypes.POINTER(ctypes.c_int64)]),

@@ -282,7 +282,8 @@ sp6_status check_state_io(sp6_grid g, const void* in, const char* nin, const voi
   return check_distinct(in, nin, out, nout, B, B);
 }
 
-sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit = false);
+sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit = false,
+                     double* Ystages = nullptr);
 
 }  // namespace
 
@@ -595,7 +596,10 @@ sp6_status ensure_radial_implicit(sp6_grid g, double dt) {
   return SP6_OK;
 }
 
-sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit) {
+// Ystages (one step, FP64): the stage inputs Y2, Y3, Y4 are written there, back
+// to back, instead of into the handle's stage buffer
+sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit,
+                     double* Ystages) {
   if (sp6_status s = check_grid(g)) return s;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
@@ -631,12 +635,13 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
         a.yin_f32 = s != 1;
         a.T = g->Tf;
       } else {
-        const double* Yin = (s == 1) ? F : g->Ybuf;
+        const double* Yin = (s == 1) ? F : (Ystages ? Ystages + size_t(s - 2) * size_t(d.P) : g->Ybuf);
         HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm), "column passes");
         a.Yin = Yin;
         a.T = g->T;
       }
       void* ybuf = mixed ? static_cast<void*>(g->Yf) : static_cast<void*>(g->Ybuf);
+      if (Ystages && s <= 3) ybuf = Ystages + size_t(s - 1) * size_t(d.P);
       switch (s) {
         case 1:
           a.accsrc = nullptr, a.accdst = g->acc, a.cb = dt / 6.0;
@@ -675,6 +680,16 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
 extern "C" {
 
 sp6_status sp6_step(sp6_grid g, double* F, double dt, int32_t nsteps) { return run_steps(g, F, dt, nsteps, nullptr); }
+
+sp6_status sp6_step_stages(sp6_grid g, double* F, double dt, double* Ystages) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "sp6_step_stages needs an FP64 handle");
+  const size_t B = state_bytes(g);
+  if (sp6_status s = check_dev(F, B, "F")) return s;
+  if (sp6_status s = check_dev(Ystages, 3 * B, "Ystages")) return s;
+  if (sp6_status s = check_distinct(F, "F", Ystages, "Ystages", B, 3 * B)) return s;
+  return run_steps(g, F, dt, 1, nullptr, false, Ystages);
+}
 
 sp6_status sp6_step_radial_implicit(sp6_grid g, double* F, double dt, int32_t nsteps) {
   return run_steps(g, F, dt, nsteps, nullptr, true);
@@ -741,13 +756,23 @@ sp6_status sp6_step_timed(sp6_grid g, double* F, double dt, int32_t nsteps, doub
   return SP6_OK;
 }
 
-sp6_status sp6_adjoint_step(sp6_grid g, const double* Fn, double dt, double* lam, double* gk, double* ge,
-                            double* gs) {
+namespace {
+
+// the discrete adjoint of one RK4 step; Ystages = null: recompute the stage
+// inputs Y2, Y3, Y4 from F_n into scratch, else read them from Ystages
+sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, double dt, double* lam, double* gk,
+                        double* ge, double* gs) {
   if (sp6_status s = check_grid(g)) return s;
   if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "adjoint_step is FP64-only");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
   if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
   if (sp6_status s = check_state_io(g, Fn, "F_n", lam, "lam")) return s;
+  if (Ystages) {
+    const size_t B3 = 3 * state_bytes(g);
+    if (sp6_status s = check_dev(Ystages, B3, "Ystages")) return s;
+    if (sp6_status s = check_distinct(Ystages, "Ystages", Fn, "F_n", B3, state_bytes(g))) return s;
+    if (sp6_status s = check_distinct(Ystages, "Ystages", lam, "lam", B3, state_bytes(g))) return s;
+  }
   const size_t cb = size_t(g->d.nplanes) * sizeof(double);
   double* gr[3] = {gk, ge, gs};
   const char* gn[3] = {"grad_kappa", "grad_eta", "grad_sigma"};
@@ -758,21 +783,28 @@ sp6_status sp6_adjoint_step(sp6_grid g, const double* Fn, double dt, double* lam
     if (sp6_status s = check_distinct(gr[i], gn[i], lam, "lam", cb, state_bytes(g))) return s;
     for (int j = 0; j < i; ++j)
       if (sp6_status s = check_distinct(gr[i], gn[i], gr[j], gn[j], cb, cb)) return s;
+    if (Ystages)
+      if (sp6_status s = check_distinct(gr[i], gn[i], Ystages, "Ystages", cb, 3 * state_bytes(g))) return s;
   }
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   const size_t B = state_bytes(g);
+  const size_t P = size_t(g->d.P);
   HIP_TRY(ensure(g, &g->T, B), "allocate scratch");
-  HIP_TRY(ensure(g, &g->Y2, B), "allocate scratch");
-  HIP_TRY(ensure(g, &g->Y3, B), "allocate scratch");
-  HIP_TRY(ensure(g, &g->Y4, B), "allocate scratch");
+  if (!Ystages) {
+    HIP_TRY(ensure(g, &g->Y2, B), "allocate scratch");
+    HIP_TRY(ensure(g, &g->Y3, B), "allocate scratch");
+    HIP_TRY(ensure(g, &g->Y4, B), "allocate scratch");
+  }
   HIP_TRY(ensure(g, &g->KB, B), "allocate scratch");
   HIP_TRY(ensure(g, &g->LACC, B), "allocate scratch");
   const KDims& d = g->d;
   if (g->desc.filter) HIP_TRY(launch_filter(d, g->t, lam, g->desc.filter == 2 ? 2 : 0, g->stream), "filter of lam");
-  // recompute the stage inputs Y2, Y3, Y4 from F_n
   double* Ys[5] = {nullptr, const_cast<double*>(Fn), g->Y2, g->Y3, g->Y4};
+  if (Ystages)
+    for (int k = 0; k < 3; ++k) Ys[k + 2] = const_cast<double*>(Ystages) + k * P;
+  // recompute the stage inputs Y2, Y3, Y4 from F_n (unless given)
   const double cn[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
-  for (int s = 1; s <= 3; ++s) {
+  for (int s = 1; s <= 3 && !Ystages; ++s) {
     bool wrote = false;
     HIP_TRY(column_terms(g, Ys[s], 7u, false, false, 1.0, &wrote), "column passes");
     StageArgs a{};
@@ -817,6 +849,19 @@ sp6_status sp6_adjoint_step(sp6_grid g, const double* Fn, double dt, double* lam
     HIP_TRY(launch_plane_adj(d, g->t, g->c, a, g->stream), "transposed plane pass");
   }
   return SP6_OK;
+}
+
+}  // namespace
+
+sp6_status sp6_adjoint_step(sp6_grid g, const double* Fn, double dt, double* lam, double* gk, double* ge,
+                            double* gs) {
+  return adjoint_core(g, Fn, nullptr, dt, lam, gk, ge, gs);
+}
+
+sp6_status sp6_adjoint_step_stages(sp6_grid g, const double* Fn, const double* Ystages, double dt, double* lam,
+                                   double* gk, double* ge, double* gs) {
+  if (!Ystages) return fail(SP6_ERR_ARG, "Ystages is NULL");
+  return adjoint_core(g, Fn, Ystages, dt, lam, gk, ge, gs);
 }
 
 sp6_status sp6_diagnostics(sp6_grid g, const double* F, double* N, double* J_in, double* J_out) {

@@ -178,6 +178,21 @@ class Sp6Grid:
                    ctypes.c_int32(nsteps), ctypes.c_int32(1 if start else 0))
         return F
 
+    def step_stages(self, F, dt, Ystages):
+        """One RK4 step in place on F that also writes its stage inputs Y2, Y3, Y4
+        into Ystages (shape (3,) + state shape)."""
+        self._call(self.lib.sp6_step_stages, _ptr(F, "F", self.shape), ctypes.c_double(dt),
+                   _ptr(Ystages, "Ystages", (3,) + self.shape))
+        return F
+
+    def adjoint_step_stages(self, F_n, Ystages, dt, lam, grad_kappa=None, grad_eta=None, grad_sigma=None):
+        """adjoint_step reading the step's stage inputs from step_stages."""
+        s = self.coef_shape
+        self._call(self.lib.sp6_adjoint_step_stages, _ptr(F_n, "F_n", self.shape),
+                   _ptr(Ystages, "Ystages", (3,) + self.shape), ctypes.c_double(dt), _ptr(lam, "lam", self.shape),
+                   _ptr(grad_kappa, "grad_kappa", s), _ptr(grad_eta, "grad_eta", s), _ptr(grad_sigma, "grad_sigma", s))
+        return lam
+
     def adjoint_step(self, F_n, dt, lam, grad_kappa=None, grad_eta=None, grad_sigma=None):
         s = self.coef_shape
         self._call(self.lib.sp6_adjoint_step, _ptr(F_n, "F_n", self.shape), ctypes.c_double(dt),

@@ -121,3 +121,61 @@ def test_workload4_gradient_vs_finite_differences():
             print(f"[gpu-test] direction {it}: adjoint {pred:.10e} fd {fd:.10e} rel {rel:.2e}", flush=True)
     banner(f"workload 4 ({n} steps, checkpoint {K}): worst |adjoint - FD| / |FD| = {worst:.2e}")
     assert worst <= 1e-6
+
+
+@pytest.mark.parametrize("filt", [0, 2])
+def test_stored_stages_match_recomputed(filt):
+    # sp6_step_stages advances F exactly as sp6_step and its stages are the RK4
+    # stage inputs; the adjoint step reading them equals the one recomputing them
+    from paper_1104_5330_amd import Sp6Grid
+    cfg = synth.config(3).scaled(n_eps=2, n_r=9, n_theta=4, n_phi=8, n_Theta=4, n_Phi=8)
+    G = Sp6Grid.from_config(cfg, filter=filt)
+    rng = np.random.default_rng(5)
+    F = synth.fields.random_state(cfg, 5)
+    k, s, e = synth.fields.random_coeffs(cfg, 6)
+    dev = torch.device("cuda")
+    G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in (k, s, e)))
+    Fa = torch.as_tensor(F, device=dev)
+    Fb = Fa.clone()
+    Ys = torch.empty((3,) + cfg.shape, dtype=torch.float64, device=dev)
+    G.step(Fa, cfg.dt, 1)
+    G.step_stages(Fb, cfg.dt, Ys)
+    assert torch.equal(Fa, Fb)
+    g = og.make_grid(*cfg.shape)
+    p = step.Physics(k, s, e, filt=bool(filt), filt_r=filt == 2)
+    Y_or, _ = step.rk4_stages(F, g, p, cfg.dt)
+    for i in range(3):
+        want = Y_or[i + 1]
+        err = np.max(np.abs(Ys[i].cpu().numpy() - want)) / np.max(np.abs(want))
+        assert err <= 1e-12, (i, err)
+    lam = torch.as_tensor(rng.normal(size=cfg.shape), device=dev)
+    z = torch.zeros(cfg.shape[:4], dtype=torch.float64, device=dev)
+    la, lb = lam.clone(), lam.clone()
+    ga = [z.clone() for _ in range(3)]
+    gb = [z.clone() for _ in range(3)]
+    F0 = torch.as_tensor(F, device=dev)
+    G.adjoint_step(F0, cfg.dt, la, *ga)
+    G.adjoint_step_stages(F0, Ys, cfg.dt, lb, *gb)
+    assert torch.equal(la, lb)
+    for x, y in zip(ga, gb):
+        assert torch.equal(x, y)
+
+
+def test_autograd_keep_stages_is_the_same():
+    from paper_1104_5330_amd.autograd import transport, outgoing_flux
+    cfg = synth.config(4).scaled(n_eps=2, n_r=9, n_theta=4, n_phi=8, n_Theta=4, n_Phi=8)
+    m = Model(cfg, 4)
+    dev = torch.device("cuda")
+    ks = torch.tensor(base_kappa_s(cfg), device=dev)
+    F0 = torch.tensor(synth.fields.shell_state(cfg), device=dev)
+    grads = []
+    for keep in (True, False):
+        kst = ks.clone().requires_grad_(True)
+        F0t = F0.clone().requires_grad_(True)
+        kappa = m.c * kst.unsqueeze(0)
+        F = transport(m.G, F0t, kappa, torch.zeros_like(kappa), kappa * m.B, cfg.dt, 10, 4, keep_stages=keep)
+        L = (outgoing_flux(m.G, F) ** 2).sum()
+        L.backward()
+        grads.append((kst.grad.clone(), F0t.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0])
+    assert torch.equal(grads[0][1], grads[1][1])
