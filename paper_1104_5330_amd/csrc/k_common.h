@@ -51,9 +51,10 @@ SP6_DEV int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 // the pass from 4.66 to 5.03 TB/s; on the radial pass's T loads and stores from
 // 4.84 to 5.0 TB/s (its stage-input loads keep the plain hint: that input is read
 // again by the plane pass, which finds it in the last-level cache); on the
-// theta-phi pass (partial-line stores) it costs 12 %, so that pass has none.
+// theta-phi pass (partial-line stores) it costs 12 %, so that pass has none; the
+// adjoint plane pass streams all its operands with it.
 #ifndef SP6_NT
-#define SP6_NT 459
+#define SP6_NT 1995
 #endif
 template <int BIT, typename T>
 SP6_DEV T ld_stream(const T* p) {
@@ -71,10 +72,10 @@ SP6_DEV void st_stream(T* p, T v) {
 }
 // plane pass: 1 stage input and T loads, 2 next-stage state (or output) stores,
 // 64 accumulator and y loads, 128 accumulator stores; radial pass: 4 stage input
-// loads, 256 T loads, 8 T stores
+// loads, 256 T loads, 8 T stores; adjoint plane pass: 512 loads, 1024 stores
 enum {
   NT_PLANE_LD = 1, NT_PLANE_ST = 2, NT_RAD_LD = 4, NT_RAD_ST = 8, NT_SPH_LD = 16, NT_SPH_ST = 32,
-  NT_PLANE_LDA = 64, NT_PLANE_STA = 128, NT_RAD_LDT = 256
+  NT_PLANE_LDA = 64, NT_PLANE_STA = 128, NT_RAD_LDT = 256, NT_ADJ_LD = 512, NT_ADJ_ST = 1024
 };
 
 // Line-operator tables in constant memory.  The Fourier derivative and the
