@@ -15,8 +15,9 @@ k_s = rhs(Y_s), the exact transpose of the step is (lam = dLoss/dy1):
 
 and the coefficient gradients are sum_s (d rhs(Y_s) / d coeff)^T kb_s, which need
 the stage inputs Y_s (recomputed from y).  With the filter on, lam is first
-mapped by the filter's transpose (the angular line filters are symmetric, the
-radial one is not).
+set to zero at the inflow nodes (when the inflow conditions are on: the step
+re-imposes the inflow values after the filter) and mapped by the filter's
+transpose (the angular line filters are symmetric, the radial one is not).
 """
 
 import numpy as np
@@ -34,6 +35,10 @@ def adjoint_step(y, lam, g, p, dt):
     if p.radial_implicit:
         raise NotImplementedError("no adjoint of the radially implicit split step")
     if p.filt:
+        # the filter step is y -> (I - P) Filter y + P g (P: the inflow nodes), whose
+        # linear part transposes to Filter^T (I - P)
+        if p.bc:
+            lam = lam * ops.inflow_mask(g)
         lam = ops.apply_filter_T(lam, g, radial=p.filt_r)
     (Y1, Y2, Y3, Y4), _ = step.rk4_stages(y, g, p, dt)
 

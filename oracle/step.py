@@ -7,7 +7,10 @@ The paper advances its spectral coefficients with second-order Adams-Bashforth
 (Sect. 5.1); this hot path uses classical fourth-order Runge-Kutta instead.
 Inflow data are constant in time, so the stages carry no explicit time.
 The optional filter (ops.apply_filter, angular lines and optionally r) is applied
-after each full step.
+after each full step; with the inflow conditions on, the inflow nodes are then
+set back to their prescribed values (Sect. 4.2: F is imposed there; a filter
+that moved them would break the boundary condition, and it makes long filtered
+runs with inflow unstable).
 """
 
 from dataclasses import dataclass
@@ -34,11 +37,24 @@ class Physics:
     radial_implicit: bool = False
     # phase function p(mu) = (1 - c2/3) + c1 mu + c2 mu^2 as (c1, c2); None = isotropic
     kernel: tuple = None
+    # inflow planes [eps][theta][phi][Theta][Phi] at r_in and r_out (None = zero),
+    # re-imposed after the filter
+    g_in: np.ndarray = None
+    g_out: np.ndarray = None
 
     @staticmethod
     def vacuum(g, bc=True):
         z = np.zeros((g.n_eps, g.n_r, g.n_theta, g.n_phi))
         return Physics(z, z.copy(), z.copy(), bc=bc, scattering=False)
+
+
+def filter_step(y, g, p):
+    """The filter after a step (ops.apply_filter), then, with the inflow
+    conditions on, the prescribed values at the inflow nodes."""
+    y = ops.apply_filter(y, g, radial=p.filt_r)
+    if p.bc:
+        y = ops.project_inflow(y, g, p.g_in, p.g_out)
+    return y
 
 
 def rhs(F, g, p):
@@ -67,7 +83,7 @@ def rk4_step(y, g, p, dt):
     if p.radial_implicit:
         y1 = ops.apply_radial_implicit(y1, g, dt, bc=p.bc)
     if p.filt:
-        y1 = ops.apply_filter(y1, g, radial=p.filt_r)
+        y1 = filter_step(y1, g, p)
     return y1
 
 
@@ -85,14 +101,18 @@ def ab2_run(y, g, p, dt, n_steps, k_prev=None):
     y_{n+1} = y_n + dt (3/2 k_n - 1/2 k_{n-1}), k_n = rhs(y_n).  Without a
     previous slope (k_prev None) the first step takes k_{-1} = k_0, i.e. forward
     Euler (the paper does not state its start).  The filter, if enabled, acts
-    on the state and on the stored slope after every step.  Returns (y, k) with k
+    on the state and on the stored slope after every step (with the inflow
+    conditions on, the state then takes its inflow values again and the slope is
+    zero at the inflow nodes, as the right-hand side is).  Returns (y, k) with k
     the stored slope, to continue a run."""
     for _ in range(n_steps):
         k = rhs(y, g, p)
         kp = k if k_prev is None else k_prev
         y = y + dt * (1.5 * k - 0.5 * kp)
         if p.filt:
-            y = ops.apply_filter(y, g, radial=p.filt_r)
+            y = filter_step(y, g, p)
             k = ops.apply_filter(k, g, radial=p.filt_r)
+            if p.bc:
+                k = k * ops.inflow_mask(g)
         k_prev = k
     return y, k_prev

@@ -101,6 +101,28 @@ hipError_t upload(sp6_grid g, const std::vector<T>& v, const T** out) {
 
 size_t state_bytes(const sp6_grid g) { return size_t(g->d.P) * sizeof(double); }
 
+// the filter after a step (Sect. 4.2: F is prescribed at the inflow nodes, so
+// with the inflow conditions on the filter is followed by the inflow values)
+hipError_t filter_step(sp6_grid g, double* F) {
+  hipError_t e = launch_filter(g->d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream);
+  if (e == hipSuccess && g->d.bc) e = launch_project(g->d, g->t, g->c, F, g->stream);
+  return e;
+}
+
+// the transpose of the linear part of filter_step, in place: zero at the inflow
+// nodes, then the transposed filter
+hipError_t filter_step_T(sp6_grid g, double* x) {
+  hipError_t e = hipSuccess;
+  if (g->d.bc) {
+    KCoef c0 = g->c;
+    c0.g_in = nullptr;
+    c0.g_out = nullptr;
+    e = launch_project(g->d, g->t, c0, x, g->stream);
+  }
+  if (e == hipSuccess) e = launch_filter(g->d, g->t, x, g->desc.filter == 2 ? 2 : 0, g->stream);
+  return e;
+}
+
 // sizes for the next theta-phi, radial or plane pass, with the traversal
 // direction flipped from the previous such pass
 const KDims& next_pass(sp6_grid g) {
@@ -668,7 +690,7 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
       if (tm) HIP_TRY(tm->mark(g->stream, KC_RADIAL), "event");
     }
     if (g->desc.filter) {
-      HIP_TRY(launch_filter(d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
+      HIP_TRY(filter_step(g, F), "filter");
       if (tm) HIP_TRY(tm->mark(g->stream, KC_FILTER), "event");
     }
   }
@@ -729,8 +751,9 @@ sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nst
     }
     HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
     if (g->desc.filter) {
-      HIP_TRY(launch_filter(d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
-      HIP_TRY(launch_filter(d, g->t, H, g->desc.filter == 2 ? 1 : 0, g->stream), "filter of H");
+      // H = F - (dt/2) k with k zero at the inflow nodes: H holds the inflow values too
+      HIP_TRY(filter_step(g, F), "filter");
+      HIP_TRY(filter_step(g, H), "filter of H");
     }
   }
   return SP6_OK;
@@ -798,7 +821,7 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
   HIP_TRY(ensure(g, &g->KB, B), "allocate scratch");
   HIP_TRY(ensure(g, &g->LACC, B), "allocate scratch");
   const KDims& d = g->d;
-  if (g->desc.filter) HIP_TRY(launch_filter(d, g->t, lam, g->desc.filter == 2 ? 2 : 0, g->stream), "filter of lam");
+  if (g->desc.filter) HIP_TRY(filter_step_T(g, lam), "transposed filter of lam");
   double* Ys[5] = {nullptr, const_cast<double*>(Fn), g->Y2, g->Y3, g->Y4};
   if (Ystages)
     for (int k = 0; k < 3; ++k) Ys[k + 2] = const_cast<double*>(Ystages) + k * P;

@@ -51,15 +51,15 @@ def setup(cfg, precision="fp64"):
     G.set_inflow(to_dev(g_in), to_dev(g_out))
     # a seeded interior plus the projected inflow (the shell experiment starts empty)
     F = ops.project_inflow(0.1 * synth.fields.polynomial_state(cfg, seed=1), oracle_grid(cfg), g_in, g_out)
-    return G, F, (k, s, e)
+    return G, F, (k, s, e), (g_in, g_out)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_shell_steps(precision):
     cfg = small(6, n_r=17, n_theta=4, n_phi=8, n_Theta=8, n_Phi=16)
-    G, F, (k, s, e) = setup(cfg, precision)
+    G, F, (k, s, e), (gi, go) = setup(cfg, precision)
     g = oracle_grid(cfg)
-    p = step.Physics(k, s, e, bc=True, scattering=True, filt=True, filt_r=True)
+    p = step.Physics(k, s, e, bc=True, scattering=True, filt=True, filt_r=True, g_in=gi, g_out=go)
     Fd = to_dev(F)
     G.step(Fd, cfg.dt, 5)
     err = maxrel(to_host(Fd), step.run(F, g, p, cfg.dt, 5))
@@ -69,9 +69,9 @@ def test_shell_steps(precision):
 
 def test_shell_adjoint():
     cfg = small(6, n_r=17, n_theta=4, n_phi=8, n_Theta=8, n_Phi=16)
-    G, F, (k, s, e) = setup(cfg)
+    G, F, (k, s, e), (gi, go) = setup(cfg)
     g = oracle_grid(cfg)
-    p = step.Physics(k, s, e, bc=True, scattering=True, filt=True, filt_r=True)
+    p = step.Physics(k, s, e, bc=True, scattering=True, filt=True, filt_r=True, g_in=gi, g_out=go)
     lam = synth.fields.random_state(cfg, 4)
     lam_prev, gk, ge, gs = adjoint.adjoint_step(F, lam, g, p, cfg.dt)
     lam_d = to_dev(lam)
@@ -97,7 +97,7 @@ def test_shell_full_size_two_steps():
     F = ops.project_inflow(np.zeros(cfg.shape), g, g_in, g_out)
     Fd = to_dev(F)
     G.step(Fd, cfg.dt, 2)
-    p = step.Physics(k, s, e, bc=True, scattering=True, filt=True, filt_r=True)
+    p = step.Physics(k, s, e, bc=True, scattering=True, filt=True, filt_r=True, g_in=g_in, g_out=g_out)
     err = maxrel(to_host(Fd), step.run(F, g, p, cfg.dt, 2))
     banner(f"{cfg.name}: 2 full-size steps vs oracle: {err:.2e}")
     assert err <= TOL
