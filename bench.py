@@ -166,6 +166,10 @@ def form_large(args):
     import synth
     cfg = synth.config(5)
     steps = max(1, min(args.steps, 10))
+    # 8.7 GB arrays: hand the earlier forms' cached blocks back first, so that the
+    # new arrays are mapped afresh (the strided theta pass is sensitive to it)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     Fm, F0, ms_m, kt_m = run_steps(cfg, "mixed", True, steps, 1)
     F64, _, ms, kt = run_steps(cfg, "fp64", True, steps, 1, F0=F0)
     del F0
