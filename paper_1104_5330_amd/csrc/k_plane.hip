@@ -197,9 +197,14 @@ constexpr int plane_waves_per_eu(int nt, bool na, bool an, int tc_bytes) {
   if (nt == 32) return 4;
   return (na && !an && tc_bytes == 8 && nt == 16) ? 4 : 1;
 }
-template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC, bool AN>
+// YM selects the base of the next stage input: 0 Yin, 1 a.ysrc, 2 the state
+// recovered from the accumulator and Yin (FP64 RK4 stage 2, where
+// acc = F + dt/6 k1 and Yin = F + dt/2 k1 give F = (3 acc - Yin) / 2)
+template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN>
 __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
+  constexpr bool NY = YM == 1, YR = YM == 2;
+  static_assert(!YR || NA, "the recovered state needs the accumulator");
   __shared__ TY sY[C::PTSP];
   __shared__ TC sR[2][C::PTSP];
   __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT], sWm[NT];
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const uint32_t p = uint32_t(tid + q * C::NTHR);
         yi[q] = ld_stream<NT_PLANE_LD>(Yb + p);
         ti[q] = needT ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && NY) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
+        if constexpr (NA && YM != 0) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
         if constexpr (NY) yo[q] = ld_stream<NT_PLANE_LDA>(Xb + p);
       }
     } else {
@@ -263,7 +268,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const bool ok = plane0 + int(p) / C::PLANE < npl;
         yi[q] = ok ? ld_stream<NT_PLANE_LD>(Yb + p) : TY(0);
         ti[q] = (ok && needT) ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && NY) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
+        if constexpr (NA && YM != 0) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
         if constexpr (NY) yo[q] = ok ? ld_stream<NT_PLANE_LDA>(Xb + p) : 0.0;
       }
     }
@@ -283,7 +288,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   };
   // the last stage (acc read, no y) loads acc for the current group after the
   // group barrier instead of one group ahead: fewer registers
-  constexpr bool NA_AHEAD = NA && NY;
+  constexpr bool NA_AHEAD = NA && YM != 0;
   TY yin[C::PPT];
   TO tn[C::PPT];
   double an[NA_AHEAD ? C::PPT : 1], yn[NY ? C::PPT : 1];
@@ -442,6 +447,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
       double ab = Yv, yb = Yv;
       if constexpr (NA) ab = av[q];
       if constexpr (NY) yb = yv[q];
+      if constexpr (YR) yb = 1.5 * ab - 0.5 * Yv;
       if (a.accdst) st_stream<NT_PLANE_STA>(a.accdst + gp, ab + a.cb * k);
       if (ynext) st_stream<NT_PLANE_ST>(ynext + gp, TO(yb + a.cn * k));
     }
@@ -681,27 +687,34 @@ unsigned persistent_blocks(const KDims& d, K kernel, int threads, int64_t work) 
   return unsigned(work < cap ? work : cap);
 }
 
-template <int NT, bool NA, bool NY, typename TY, typename TO, typename TC, bool AN>
+template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN>
 void launch_plane_t(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   const int ng = int((d.nplanes + PC<NT>::NPW - 1) / PC<NT>::NPW);
-  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, NY, TY, TO, TC, AN>, PC<NT>::NTHR, ng);
-  k_plane<NT, NA, NY, TY, TO, TC, AN><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
+  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, YM, TY, TO, TC, AN>, PC<NT>::NTHR, ng);
+  k_plane<NT, NA, YM, TY, TO, TC, AN><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
 }
 
 template <int NT, typename TY, typename TO, typename TC>
 void launch_plane_nt(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
   const bool an = d.scattering && c.aniso && a.mode != PM_APPLY;
+  if constexpr (sizeof(TY) == 8 && sizeof(TO) == 8) {
+    if (a.yrec) {  // checked by launch_plane: accumulator given, no ysrc
+      if (an) launch_plane_t<NT, true, 2, TY, TO, TC, true>(d, t, c, a, s);
+      else launch_plane_t<NT, true, 2, TY, TO, TC, false>(d, t, c, a, s);
+      return;
+    }
+  }
   if (an) {
-    if (na && ny) launch_plane_t<NT, true, true, TY, TO, TC, true>(d, t, c, a, s);
-    else if (na) launch_plane_t<NT, true, false, TY, TO, TC, true>(d, t, c, a, s);
-    else if (ny) launch_plane_t<NT, false, true, TY, TO, TC, true>(d, t, c, a, s);
-    else launch_plane_t<NT, false, false, TY, TO, TC, true>(d, t, c, a, s);
+    if (na && ny) launch_plane_t<NT, true, 1, TY, TO, TC, true>(d, t, c, a, s);
+    else if (na) launch_plane_t<NT, true, 0, TY, TO, TC, true>(d, t, c, a, s);
+    else if (ny) launch_plane_t<NT, false, 1, TY, TO, TC, true>(d, t, c, a, s);
+    else launch_plane_t<NT, false, 0, TY, TO, TC, true>(d, t, c, a, s);
   } else {
-    if (na && ny) launch_plane_t<NT, true, true, TY, TO, TC, false>(d, t, c, a, s);
-    else if (na) launch_plane_t<NT, true, false, TY, TO, TC, false>(d, t, c, a, s);
-    else if (ny) launch_plane_t<NT, false, true, TY, TO, TC, false>(d, t, c, a, s);
-    else launch_plane_t<NT, false, false, TY, TO, TC, false>(d, t, c, a, s);
+    if (na && ny) launch_plane_t<NT, true, 1, TY, TO, TC, false>(d, t, c, a, s);
+    else if (na) launch_plane_t<NT, true, 0, TY, TO, TC, false>(d, t, c, a, s);
+    else if (ny) launch_plane_t<NT, false, 1, TY, TO, TC, false>(d, t, c, a, s);
+    else launch_plane_t<NT, false, 0, TY, TO, TC, false>(d, t, c, a, s);
   }
 }
 
@@ -716,6 +729,7 @@ void launch_plane_n(const KDims& d, const KTab& t, const KCoef& c, const StageAr
 }
 
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
+  if (a.yrec && (a.mixed || a.mode != PM_STAGE || !a.accsrc || a.ysrc)) return hipErrorInvalidValue;
   switch (d.n_Th) {
 #define CASE(N)                          \
   case N:                                \

@@ -98,13 +98,15 @@ struct StageArgs {
   const void* Yin;       // stage input
   const void* T;         // sum of the r, theta, phi terms of L Yin (may be null = 0)
   double* out;           // PM_APPLY / PM_RHS output
-  // PM_STAGE: accdst = (accsrc ? accsrc : Yin) + cb * k ; ynext = (ysrc ? ysrc : Yin) + cn * k
+  // PM_STAGE: accdst = (accsrc ? accsrc : Yin) + cb * k ; ynext = (ysrc ? ysrc : Yin) + cn * k,
+  // or with yrec (FP64, accsrc given, no ysrc) ynext = (1.5 accsrc - 0.5 Yin) + cn * k
   const double* accsrc;
   double* accdst;
   double cb;
   const double* ysrc;
   void* ynext;
   double cn;
+  int yrec;
   uint32_t terms;        // bit 3 Theta, bit 4 Phi
   int mixed;             // 0: FP64 path; 1: mixed path
   int yin_f32;           // mixed path: Yin is FP32
