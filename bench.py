@@ -40,12 +40,12 @@ METRIC = "6D grid-point updates/s per RK4 step (FP64 vs mixed vs adjoint), % HBM
 #   phi    : read Y, write T                                   16
 #   theta  : read Y, T, write T                                24
 #   radial : read Y, T, write T                                24
-#   plane  : stage 1 read Y, T; write acc, Y'                  32
-#            stage 2 read Y, T, acc; write acc, Y'             40
-#              (y recovered from acc and Y)
+#   plane  : stage 1 read Y, T; write Y'                       24
+#            stage 2 read Y, T, y; write acc, Y'               40
+#              (acc's base y + (Y - y)/3 recovered, not read)
 #            stage 3 read Y, T, y, acc; write acc, Y'          48
-#            stage 4 read Y, T, acc; write y                   32   -> mean 38
-BYTES_FP64 = {"thetaphi": 16.0, "phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 38.0}
+#            stage 4 read Y, T, acc; write y                   32   -> mean 36
+BYTES_FP64 = {"thetaphi": 16.0, "phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 36.0}
 # Mixed path (stage copy and T in FP32; stage 1 reads the FP64 state):
 #   thetaphi, phi : (8 + 4, then 3 x (4 + 4)) / 4                9
 #   theta  : (8 + 4 + 4, then 3 x 12) / 4                       13

@@ -668,13 +668,14 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
         case 1:
           a.accsrc = nullptr, a.accdst = g->acc, a.cb = dt / 6.0;
           a.ysrc = nullptr, a.ynext = ybuf, a.cn = 0.5 * dt;
+          // FP64: the accumulator is first written in stage 2, from F and
+          // Y2 = F + dt/2 k1 (8 of 32 bytes per point)
+          if (!mixed) a.accdst = nullptr;
           break;
         case 2:
           a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
           a.ysrc = F, a.ynext = ybuf, a.cn = 0.5 * dt;
-          // FP64: F is recovered from acc = F + dt/6 k1 and Yin = F + dt/2 k1
-          // instead of being read (8 of 48 bytes per point)
-          if (!mixed) a.ysrc = nullptr, a.yrec = 1;
+          if (!mixed) a.accsrc = nullptr, a.accrec = 1;
           break;
         case 3:
           a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
@@ -828,11 +829,8 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
   double* Ys[5] = {nullptr, const_cast<double*>(Fn), g->Y2, g->Y3, g->Y4};
   if (Ystages)
     for (int k = 0; k < 3; ++k) Ys[k + 2] = const_cast<double*>(Ystages) + k * P;
-  // recompute the stage inputs Y2, Y3, Y4 from F_n (unless given), with the
-  // arithmetic of the forward step (Y3 from the state recovered from
-  // acc = F_n + dt/6 k1 and Y2), so that they equal its stages bit for bit
+  // recompute the stage inputs Y2, Y3, Y4 from F_n (unless given)
   const double cn[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
-  if (!Ystages) HIP_TRY(ensure(g, &g->acc, B), "allocate scratch");
   for (int s = 1; s <= 3 && !Ystages; ++s) {
     bool wrote = false;
     HIP_TRY(column_terms(g, Ys[s], 7u, false, false, 1.0, &wrote), "column passes");
@@ -841,9 +839,7 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
     a.Yin = Ys[s];
     a.T = g->T;
     a.terms = 31u;
-    a.ysrc = (s == 3) ? Fn : nullptr;
-    if (s == 1) a.accdst = g->acc, a.cb = dt / 6.0;
-    if (s == 2) a.accsrc = g->acc, a.yrec = 1;
+    a.ysrc = (s == 1) ? nullptr : Fn;
     a.ynext = Ys[s + 1];
     a.cn = cn[s];
     HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");

@@ -189,22 +189,24 @@ struct PlaneInfo {
 // input, TC: type of the line derivatives.  The collision term, the inflow mask
 // and the RK update are FP64 in every instantiation.
 // AN: anisotropic scattering (plane moments instead of the angular mean).
-// FP64 stages that read the accumulator (2, 3 and 4) on 16 x 32 planes: capped at
-// 128 VGPRs for four waves per SIMD (measured 536 -> 528 us for the pass; stages
-// 2 and 3 then spill a few registers).  2048-point planes (eight wavefronts per
-// workgroup): 128 VGPRs, so that two workgroups share a CU.
-constexpr int plane_waves_per_eu(int nt, bool na, bool an, int tc_bytes) {
+// FP64 stages 2, 3 and 4 on 16 x 32 planes: capped at 128 VGPRs for four waves
+// per SIMD (measured 536 -> 528 us for the pass; 1 % of the step for stage 2 in
+// its form without the accumulator read; stages 2 and 3 then spill a few
+// registers).  Stage 1 is as fast either way.  2048-point planes (eight
+// wavefronts per workgroup): 128 VGPRs, so that two workgroups share a CU.
+constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes) {
   if (nt == 32) return 4;
-  return (na && !an && tc_bytes == 8 && nt == 16) ? 4 : 1;
+  return ((na || ym == 2) && !an && tc_bytes == 8 && nt == 16) ? 4 : 1;
 }
-// YM selects the base of the next stage input: 0 Yin, 1 a.ysrc, 2 the state
-// recovered from the accumulator and Yin (FP64 RK4 stage 2, where
-// acc = F + dt/6 k1 and Yin = F + dt/2 k1 give F = (3 acc - Yin) / 2)
+// YM: 0 the next stage input is based on Yin; 1 on a.ysrc; 2 on a.ysrc, and the
+// accumulator's base is recovered from Yin and a.ysrc (FP64 RK4 stage 2, where
+// Yin = F + dt/2 k1 and ysrc = F give F + dt/6 k1 = ysrc + (Yin - ysrc) / 3, so
+// stage 1 need not write the accumulator)
 template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN>
-__global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
+__global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, YM, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
-  constexpr bool NY = YM == 1, YR = YM == 2;
-  static_assert(!YR || NA, "the recovered state needs the accumulator");
+  constexpr bool NY = YM != 0, YR = YM == 2;
+  static_assert(!YR || !NA, "the accumulator base is either loaded or recovered");
   __shared__ TY sY[C::PTSP];
   __shared__ TC sR[2][C::PTSP];
   __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT], sWm[NT];
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const uint32_t p = uint32_t(tid + q * C::NTHR);
         yi[q] = ld_stream<NT_PLANE_LD>(Yb + p);
         ti[q] = needT ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && YM != 0) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
+        if constexpr (NA && NY) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
         if constexpr (NY) yo[q] = ld_stream<NT_PLANE_LDA>(Xb + p);
       }
     } else {
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const bool ok = plane0 + int(p) / C::PLANE < npl;
         yi[q] = ok ? ld_stream<NT_PLANE_LD>(Yb + p) : TY(0);
         ti[q] = (ok && needT) ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && YM != 0) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
+        if constexpr (NA && NY) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
         if constexpr (NY) yo[q] = ok ? ld_stream<NT_PLANE_LDA>(Xb + p) : 0.0;
       }
     }
@@ -288,7 +290,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   };
   // the last stage (acc read, no y) loads acc for the current group after the
   // group barrier instead of one group ahead: fewer registers
-  constexpr bool NA_AHEAD = NA && YM != 0;
+  constexpr bool NA_AHEAD = NA && NY;
   TY yin[C::PPT];
   TO tn[C::PPT];
   double an[NA_AHEAD ? C::PPT : 1], yn[NY ? C::PPT : 1];
@@ -447,7 +449,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
       double ab = Yv, yb = Yv;
       if constexpr (NA) ab = av[q];
       if constexpr (NY) yb = yv[q];
-      if constexpr (YR) yb = 1.5 * ab - 0.5 * Yv;
+      if constexpr (YR) ab = yb + (Yv - yb) * (1.0 / 3.0);
       if (a.accdst) st_stream<NT_PLANE_STA>(a.accdst + gp, ab + a.cb * k);
       if (ynext) st_stream<NT_PLANE_ST>(ynext + gp, TO(yb + a.cn * k));
     }
@@ -699,9 +701,9 @@ void launch_plane_nt(const KDims& d, const KTab& t, const KCoef& c, const StageA
   const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
   const bool an = d.scattering && c.aniso && a.mode != PM_APPLY;
   if constexpr (sizeof(TY) == 8 && sizeof(TO) == 8) {
-    if (a.yrec) {  // checked by launch_plane: accumulator given, no ysrc
-      if (an) launch_plane_t<NT, true, 2, TY, TO, TC, true>(d, t, c, a, s);
-      else launch_plane_t<NT, true, 2, TY, TO, TC, false>(d, t, c, a, s);
+    if (a.accrec) {  // checked by launch_plane: ysrc given, no accumulator source
+      if (an) launch_plane_t<NT, false, 2, TY, TO, TC, true>(d, t, c, a, s);
+      else launch_plane_t<NT, false, 2, TY, TO, TC, false>(d, t, c, a, s);
       return;
     }
   }
@@ -729,7 +731,7 @@ void launch_plane_n(const KDims& d, const KTab& t, const KCoef& c, const StageAr
 }
 
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
-  if (a.yrec && (a.mixed || a.mode != PM_STAGE || !a.accsrc || a.ysrc)) return hipErrorInvalidValue;
+  if (a.accrec && (a.mixed || a.mode != PM_STAGE || a.accsrc || !a.ysrc)) return hipErrorInvalidValue;
   switch (d.n_Th) {
 #define CASE(N)                          \
   case N:                                \

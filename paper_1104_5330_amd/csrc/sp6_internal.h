@@ -99,14 +99,14 @@ struct StageArgs {
   const void* T;         // sum of the r, theta, phi terms of L Yin (may be null = 0)
   double* out;           // PM_APPLY / PM_RHS output
   // PM_STAGE: accdst = (accsrc ? accsrc : Yin) + cb * k ; ynext = (ysrc ? ysrc : Yin) + cn * k,
-  // or with yrec (FP64, accsrc given, no ysrc) ynext = (1.5 accsrc - 0.5 Yin) + cn * k
+  // or with accrec (FP64, ysrc given, no accsrc) accdst = (ysrc + (Yin - ysrc) / 3) + cb * k
   const double* accsrc;
   double* accdst;
   double cb;
   const double* ysrc;
   void* ynext;
   double cn;
-  int yrec;
+  int accrec;
   uint32_t terms;        // bit 3 Theta, bit 4 Phi
   int mixed;             // 0: FP64 path; 1: mixed path
   int yin_f32;           // mixed path: Yin is FP32
