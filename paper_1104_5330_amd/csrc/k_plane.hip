@@ -192,11 +192,14 @@ struct PlaneInfo {
 // FP64 stages 2, 3 and 4 on 16 x 32 planes: capped at 128 VGPRs for four waves
 // per SIMD (measured 536 -> 528 us for the pass; 1 % of the step for stage 2 in
 // its form without the accumulator read; stages 2 and 3 then spill a few
-// registers).  Stage 1 is as fast either way.  2048-point planes (eight
+// registers).  Stage 1, the lightest, at five waves per SIMD (0.7 % of the step;
+// six spill, and five for stage 4 gain nothing).  2048-point planes (eight
 // wavefronts per workgroup): 128 VGPRs, so that two workgroups share a CU.
 constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes) {
   if (nt == 32) return 4;
-  return ((na || ym == 2) && !an && tc_bytes == 8 && nt == 16) ? 4 : 1;
+  if (!(!an && tc_bytes == 8 && nt == 16)) return 1;
+  if (!na) return ym == 0 ? 5 : (ym == 2 ? 4 : 1);
+  return 4;
 }
 // YM: 0 the next stage input is based on Yin; 1 on a.ysrc; 2 on a.ysrc, and the
 // accumulator's base is recovered from Yin and a.ysrc (FP64 RK4 stage 2, where
