@@ -193,10 +193,13 @@ struct PlaneInfo {
 // per SIMD (measured 536 -> 528 us for the pass; 1 % of the step for stage 2 in
 // its form without the accumulator read; stages 2 and 3 then spill a few
 // registers).  Stage 1, the lightest, at five waves per SIMD (0.7 % of the step;
-// six spill, and five for stage 4 gain nothing).  2048-point planes (eight
+// six spill, and five for stage 4 gain nothing).  The anisotropic FP64 pass (ten
+// plane moments) at three waves per SIMD: 694 -> 625 us (four: no gain).  The
+// mixed pass is as fast at one to four.  2048-point planes (eight
 // wavefronts per workgroup): 128 VGPRs, so that two workgroups share a CU.
 constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes) {
   if (nt == 32) return 4;
+  if (nt == 16 && an && tc_bytes == 8) return 3;
   if (!(!an && tc_bytes == 8 && nt == 16)) return 1;
   if (!na) return ym == 0 ? 5 : (ym == 2 ? 4 : 1);
   return 4;
