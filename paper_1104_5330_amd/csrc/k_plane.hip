@@ -29,6 +29,8 @@ SP6_DEV const TC* line_tab(int kind) {
     return c_lines_f + kind * LINE_TAB_SIZE + line_tab_offset(L);
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <int NT>
 struct PC {
   static constexpr int L = 2 * NT;        // line length (Theta DFS line, Phi row)
@@ -192,8 +194,9 @@ struct PlaneInfo {
 // FP64 stages 2, 3 and 4 on 16 x 32 planes: capped at 128 VGPRs for four waves
 // per SIMD (measured 536 -> 528 us for the pass; 1 % of the step for stage 2 in
 // its form without the accumulator read; stages 2 and 3 then spill a few
-// registers).  Stage 1, the lightest, at five waves per SIMD (0.7 % of the step;
-// six spill, and five for stage 4 gain nothing).  The anisotropic FP64 pass (ten
+// registers).  Stage 1, the lightest, at four as well: with its lines on MFMA
+// (below) five spill; with streamed lines five gained 0.7 %, six spilled, and
+// five for stage 4 gained nothing.  The anisotropic FP64 pass (ten
 // plane moments) at three waves per SIMD: 694 -> 625 us (four: no gain).  The
 // mixed pass is as fast at one to four.  2048-point planes (eight
 // wavefronts per workgroup): 128 VGPRs, so that two workgroups share a CU.
@@ -201,8 +204,7 @@ constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes)
   if (nt == 32) return 4;
   if (nt == 16 && an && tc_bytes == 8) return 3;
   if (!(!an && tc_bytes == 8 && nt == 16)) return 1;
-  if (!na) return ym == 0 ? 5 : (ym == 2 ? 4 : 1);
-  return 4;
+  return (!na && ym == 1) ? 1 : 4;
 }
 // YM: 0 the next stage input is based on Yin; 1 on a.ysrc; 2 on a.ysrc, and the
 // accumulator's base is recovered from Yin and a.ysrc (FP64 RK4 stage 2, where
@@ -222,6 +224,21 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
 
   const int tid = threadIdx.x;
   const int npl = int(d.nplanes);
+  // FP64 lines on 16 x 32 planes in the variant without accumulator or y
+  // operands (RK stage 1, the right-hand side, L): the even and odd halves of the
+  // Theta and Phi line operators as 16 x 16 x 16 products on
+  // v_mfma_f64_16x16x4f64 (wavefront w takes direction w mod 2 of plane w div 2),
+  // with the transposed even (first) and odd (second) blocks of the table staged
+  // in LDS.  Each staged value is then read from LDS twice per point instead of
+  // eight times (stage 1 of the step: 0.7 % faster).  The variants that also
+  // hold the accumulator and y operands spill under their 128-register cap with
+  // it and lose (plane pass 485 -> 526 us), so they stream the lines.
+  constexpr bool MFL = NT == 16 && sizeof(TY) == 8 && sizeof(TC) == 8 && C::NW == 4 && C::NPW == 2 && !NA && YM == 0;
+  __shared__ double sTab[MFL ? 2 * NT * NT : 1];
+  if constexpr (MFL) {
+    const double* tab = line_tab<C::L, double>(LT_DERIV_T);
+    for (int i = tid; i < 2 * NT * NT; i += C::NTHR) sTab[i] = tab[i];
+  }
   if (tid < NT) {
     sTh[tid] = t.sin_Th[tid];
     sCT[tid] = t.cos_Th[tid];
@@ -414,12 +431,52 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         s = plane_rows_sum<NT>(s);
         if (li == NT) sPl[pl].mean = s;
       }
-      TC* out = sR[isTh ? 0 : 1];
-      // the line is streamed from LDS against the transposed table instead of
-      // being held in registers: fewer registers, higher occupancy
-      eo_pairs_stream<C::L, C::PPW, true, TC, 2>(
-          line_tab<C::L, TC>(LT_DERIV_T), part * C::PPW, [&](int q) { return TC(sY[lm.idx(q)]); },
-          [&](int q, TC z) { out[lm.idx(q)] = TC(line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh)) * z; });
+      if constexpr (MFL) {
+        // Theta (w even): P = A^T E, Q = B^T O with E, O = Y[j][c] +- Y[j][c + 16]
+        // (the DFS line of column c and its reversed partner half); Phi (w odd):
+        // P = E A, Q = O B with E, O = Y[i][j] +- Y[i][31 - j].  Outputs q and
+        // 31 - q of a line are P + Q and Q - P.
+        const int mp = part >> 1;
+        const bool th = (part & 1) == 0;
+        const int lr = lane & 15, lk = lane >> 4;
+        const int pb = mp * C::PS;
+        v4d cp = {0.0, 0.0, 0.0, 0.0}, cq = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+        for (int k = 0; k < NT / 4; ++k) {
+          const int j = 4 * k + lk;
+          const double ta = sTab[j * NT + lr], tb = sTab[NT * NT + j * NT + lr];
+          if (th) {
+            const double x = double(sY[pb + j * C::RS + lr]), y = double(sY[pb + j * C::RS + lr + NT]);
+            cp = __builtin_amdgcn_mfma_f64_16x16x4f64(ta, x + y, cp, 0, 0, 0);
+            cq = __builtin_amdgcn_mfma_f64_16x16x4f64(tb, x - y, cq, 0, 0, 0);
+          } else {
+            const double x = double(sY[pb + lr * C::RS + j]), y = double(sY[pb + lr * C::RS + (C::L - 1 - j)]);
+            cp = __builtin_amdgcn_mfma_f64_16x16x4f64(x + y, ta, cp, 0, 0, 0);
+            cq = __builtin_amdgcn_mfma_f64_16x16x4f64(x - y, tb, cq, 0, 0, 0);
+          }
+        }
+        const double ir = sPl[mp].inv_r, ct = sPl[mp].cot_th;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = lk + 4 * v;  // C row: output index (Theta) or plane row (Phi)
+          const double pv = cp[v] + cq[v], qv = cq[v] - cp[v];
+          if (th) {  // line = column lr; outputs a and 31 - a (row a of column lr + 16)
+            sR[0][pb + a * C::RS + lr] = TC(line_coef<NT>(true, a, lr, ir, ct, sTh, sPh) * pv);
+            sR[0][pb + a * C::RS + lr + NT] = TC(line_coef<NT>(true, C::L - 1 - a, lr, ir, ct, sTh, sPh) * qv);
+          } else {  // row a; outputs lr and 31 - lr
+            sR[1][pb + a * C::RS + lr] = TC(line_coef<NT>(false, lr, NT + a, ir, ct, sTh, sPh) * pv);
+            sR[1][pb + a * C::RS + (C::L - 1 - lr)] =
+                TC(line_coef<NT>(false, C::L - 1 - lr, NT + a, ir, ct, sTh, sPh) * qv);
+          }
+        }
+      } else {
+        TC* out = sR[isTh ? 0 : 1];
+        // the line is streamed from LDS against the transposed table instead of
+        // being held in registers: fewer registers, higher occupancy
+        eo_pairs_stream<C::L, C::PPW, true, TC, 2>(
+            line_tab<C::L, TC>(LT_DERIV_T), part * C::PPW, [&](int q) { return TC(sY[lm.idx(q)]); },
+            [&](int q, TC z) { out[lm.idx(q)] = TC(line_coef<NT>(isTh, q, li, inv_r, cot_th, sTh, sPh)) * z; });
+      }
     }
     __syncthreads();
 
