@@ -191,12 +191,11 @@ struct PlaneInfo {
 // input, TC: type of the line derivatives.  The collision term, the inflow mask
 // and the RK update are FP64 in every instantiation.
 // AN: anisotropic scattering (plane moments instead of the angular mean).
-// FP64 stages 2, 3 and 4 on 16 x 32 planes: capped at 128 VGPRs for four waves
-// per SIMD (measured 536 -> 528 us for the pass; 1 % of the step for stage 2 in
-// its form without the accumulator read; stages 2 and 3 then spill a few
-// registers).  Stage 1, the lightest, at four as well: with its lines on MFMA
-// (below) five spill; with streamed lines five gained 0.7 %, six spilled, and
-// five for stage 4 gained nothing.  The anisotropic FP64 pass (ten
+// FP64 on 16 x 32 planes, lines on MFMA: stage 1 (no accumulator or y
+// operands) at four waves per SIMD (128 VGPRs, no spills; five spill), stages
+// 2, 3 and 4 at three (168 VGPRs: at four they spill and the pass went from 485
+// to 526 us; at two they are no faster).  With the lines streamed from LDS the
+// best caps had been five for stage 1 and four for the others.  The anisotropic FP64 pass (ten
 // plane moments) at three waves per SIMD: 694 -> 625 us (four: no gain).  The
 // mixed pass is as fast at one to four.  2048-point planes (eight
 // wavefronts per workgroup): 128 VGPRs, so that two workgroups share a CU.
@@ -204,7 +203,8 @@ constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes)
   if (nt == 32) return 4;
   if (nt == 16 && an && tc_bytes == 8) return 3;
   if (!(!an && tc_bytes == 8 && nt == 16)) return 1;
-  return (!na && ym == 1) ? 1 : 4;
+  if (!na) return ym == 0 ? 4 : (ym == 1 ? 1 : 3);
+  return 3;
 }
 // YM: 0 the next stage input is based on Yin; 1 on a.ysrc; 2 on a.ysrc, and the
 // accumulator's base is recovered from Yin and a.ysrc (FP64 RK4 stage 2, where
@@ -224,16 +224,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
 
   const int tid = threadIdx.x;
   const int npl = int(d.nplanes);
-  // FP64 lines on 16 x 32 planes in the variant without accumulator or y
-  // operands (RK stage 1, the right-hand side, L): the even and odd halves of the
-  // Theta and Phi line operators as 16 x 16 x 16 products on
-  // v_mfma_f64_16x16x4f64 (wavefront w takes direction w mod 2 of plane w div 2),
-  // with the transposed even (first) and odd (second) blocks of the table staged
-  // in LDS.  Each staged value is then read from LDS twice per point instead of
-  // eight times (stage 1 of the step: 0.7 % faster).  The variants that also
-  // hold the accumulator and y operands spill under their 128-register cap with
-  // it and lose (plane pass 485 -> 526 us), so they stream the lines.
-  constexpr bool MFL = NT == 16 && sizeof(TY) == 8 && sizeof(TC) == 8 && C::NW == 4 && C::NPW == 2 && !NA && YM == 0;
+  // FP64 lines on 16 x 32 planes: the even and odd halves of the Theta and Phi
+  // line operators as 16 x 16 x 16 products on v_mfma_f64_16x16x4f64 (wavefront
+  // w takes direction w mod 2 of plane w div 2), with the transposed even (first)
+  // and odd (second) blocks of the table staged in LDS.  Each staged value is
+  // read from LDS twice per point instead of eight times (RK4 step 2 % faster).
+  constexpr bool MFL = NT == 16 && sizeof(TY) == 8 && sizeof(TC) == 8 && C::NW == 4 && C::NPW == 2;
   __shared__ double sTab[MFL ? 2 * NT * NT : 1];
   if constexpr (MFL) {
     const double* tab = line_tab<C::L, double>(LT_DERIV_T);
