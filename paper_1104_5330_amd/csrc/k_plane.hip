@@ -10,6 +10,8 @@
 // eta - (kappa + sigma) F + sigma <F> (Eq. Transp with an isotropic kernel,
 // <F> with Fejer weights in cos Theta), the inflow mask (Sect. 4.2) and the RK4
 // stage update, all in FP64.
+#include <type_traits>
+
 #include "k_common.h"
 
 namespace {
@@ -30,6 +32,7 @@ SP6_DEV const TC* line_tab(int kind) {
 }
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 template <int NT>
 struct PC {
@@ -224,15 +227,17 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
 
   const int tid = threadIdx.x;
   const int npl = int(d.nplanes);
-  // FP64 lines on 16 x 32 planes: the even and odd halves of the Theta and Phi
-  // line operators as 16 x 16 x 16 products on v_mfma_f64_16x16x4f64 (wavefront
-  // w takes direction w mod 2 of plane w div 2), with the transposed even (first)
-  // and odd (second) blocks of the table staged in LDS.  Each staged value is
-  // read from LDS twice per point instead of eight times (RK4 step 2 % faster).
-  constexpr bool MFL = NT == 16 && sizeof(TY) == 8 && sizeof(TC) == 8 && C::NW == 4 && C::NPW == 2;
-  __shared__ double sTab[MFL ? 2 * NT * NT : 1];
+  // Lines on 16 x 32 planes: the even and odd halves of the Theta and Phi line
+  // operators as 16 x 16 x 16 products on v_mfma_f64_16x16x4f64 (FP64 path) or
+  // v_mfma_f32_16x16x4f32 (mixed path), wavefront w taking direction w mod 2 of
+  // plane w div 2, with the transposed even (first) and odd (second) blocks of
+  // the table staged in LDS.  Each staged value is read from LDS twice per point
+  // instead of eight times (FP64 RK4 step 2 % faster, mixed 1 %).
+  constexpr bool MFL = NT == 16 && C::NW == 4 && C::NPW == 2 &&
+                       ((sizeof(TY) == 8 && sizeof(TC) == 8) || sizeof(TC) == 4);
+  __shared__ TC sTab[MFL ? 2 * NT * NT : 1];
   if constexpr (MFL) {
-    const double* tab = line_tab<C::L, double>(LT_DERIV_T);
+    const TC* tab = line_tab<C::L, TC>(LT_DERIV_T);
     for (int i = tid; i < 2 * NT * NT; i += C::NTHR) sTab[i] = tab[i];
   }
   if (tid < NT) {
@@ -436,26 +441,35 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const bool th = (part & 1) == 0;
         const int lr = lane & 15, lk = lane >> 4;
         const int pb = mp * C::PS;
-        v4d cp = {0.0, 0.0, 0.0, 0.0}, cq = {0.0, 0.0, 0.0, 0.0};
+        using VC = typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type;
+        VC cp = {0, 0, 0, 0}, cq = {0, 0, 0, 0};
+        auto mfma = [](TC a, TC b, VC c) {
+          if constexpr (sizeof(TC) == 8)
+            return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+          else
+            return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        };
 #pragma unroll 1
         for (int k = 0; k < NT / 4; ++k) {
           const int j = 4 * k + lk;
-          const double ta = sTab[j * NT + lr], tb = sTab[NT * NT + j * NT + lr];
+          const TC ta = sTab[j * NT + lr], tb = sTab[NT * NT + j * NT + lr];
           if (th) {
-            const double x = double(sY[pb + j * C::RS + lr]), y = double(sY[pb + j * C::RS + lr + NT]);
-            cp = __builtin_amdgcn_mfma_f64_16x16x4f64(ta, x + y, cp, 0, 0, 0);
-            cq = __builtin_amdgcn_mfma_f64_16x16x4f64(tb, x - y, cq, 0, 0, 0);
+            const TC x = TC(sY[pb + j * C::RS + lr]), y = TC(sY[pb + j * C::RS + lr + NT]);
+            cp = mfma(ta, x + y, cp);
+            cq = mfma(tb, x - y, cq);
           } else {
-            const double x = double(sY[pb + lr * C::RS + j]), y = double(sY[pb + lr * C::RS + (C::L - 1 - j)]);
-            cp = __builtin_amdgcn_mfma_f64_16x16x4f64(x + y, ta, cp, 0, 0, 0);
-            cq = __builtin_amdgcn_mfma_f64_16x16x4f64(x - y, tb, cq, 0, 0, 0);
+            const TC x = TC(sY[pb + lr * C::RS + j]), y = TC(sY[pb + lr * C::RS + (C::L - 1 - j)]);
+            cp = mfma(x + y, ta, cp);
+            cq = mfma(x - y, tb, cq);
           }
         }
         const double ir = sPl[mp].inv_r, ct = sPl[mp].cot_th;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int a = lk + 4 * v;  // C row: output index (Theta) or plane row (Phi)
-          const double pv = cp[v] + cq[v], qv = cq[v] - cp[v];
+          // C row (output index for Theta, plane row for Phi): interleaved for
+          // the FP64 product, in blocks of four for the FP32 one
+          const int a = sizeof(TC) == 8 ? lk + 4 * v : 4 * lk + v;
+          const TC pv = cp[v] + cq[v], qv = cq[v] - cp[v];
           if (th) {  // line = column lr; outputs a and 31 - a (row a of column lr + 16)
             sR[0][pb + a * C::RS + lr] = TC(line_coef<NT>(true, a, lr, ir, ct, sTh, sPh) * pv);
             sR[0][pb + a * C::RS + lr + NT] = TC(line_coef<NT>(true, C::L - 1 - a, lr, ir, ct, sTh, sPh) * qv);
