@@ -212,12 +212,14 @@ constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes)
 // YM: 0 the next stage input is based on Yin; 1 on a.ysrc; 2 on a.ysrc, and the
 // accumulator's base is recovered from Yin and a.ysrc (FP64 RK4 stage 2, where
 // Yin = F + dt/2 k1 and ysrc = F give F + dt/6 k1 = ysrc + (Yin - ysrc) / 3, so
-// stage 1 need not write the accumulator)
+// stage 1 need not write the accumulator); 4 on the accumulator source itself
+// (Adams-Bashforth, whose history H is both: loaded once)
 template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN>
 __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, YM, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
-  constexpr bool NY = YM != 0, YR = YM == 2;
+  constexpr bool NY = YM == 1 || YM == 2, YR = YM == 2, YA = YM == 4;
   static_assert(!YR || !NA, "the accumulator base is either loaded or recovered");
+  static_assert(!YA || NA, "y is the loaded accumulator");
   __shared__ TY sY[C::PTSP];
   __shared__ TC sR[2][C::PTSP];
   __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT], sWm[NT];
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const uint32_t p = uint32_t(tid + q * C::NTHR);
         yi[q] = ld_stream<NT_PLANE_LD>(Yb + p);
         ti[q] = needT ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && NY) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
+        if constexpr (NA && (NY || YA)) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
         if constexpr (NY) yo[q] = ld_stream<NT_PLANE_LDA>(Xb + p);
       }
     } else {
@@ -294,7 +296,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const bool ok = plane0 + int(p) / C::PLANE < npl;
         yi[q] = ok ? ld_stream<NT_PLANE_LD>(Yb + p) : TY(0);
         ti[q] = (ok && needT) ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && NY) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
+        if constexpr (NA && (NY || YA)) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
         if constexpr (NY) yo[q] = ok ? ld_stream<NT_PLANE_LDA>(Xb + p) : 0.0;
       }
     }
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   };
   // the last stage (acc read, no y) loads acc for the current group after the
   // group barrier instead of one group ahead: fewer registers
-  constexpr bool NA_AHEAD = NA && NY;
+  constexpr bool NA_AHEAD = NA && (NY || YA);
   TY yin[C::PPT];
   TO tn[C::PPT];
   double an[NA_AHEAD ? C::PPT : 1], yn[NY ? C::PPT : 1];
@@ -523,6 +525,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
       if constexpr (NA) ab = av[q];
       if constexpr (NY) yb = yv[q];
       if constexpr (YR) ab = yb + (Yv - yb) * (1.0 / 3.0);
+      if constexpr (YA) yb = ab;
       if (a.accdst) st_stream<NT_PLANE_STA>(a.accdst + gp, ab + a.cb * k);
       if (ynext) st_stream<NT_PLANE_ST>(ynext + gp, TO(yb + a.cn * k));
     }
@@ -822,6 +825,11 @@ void launch_plane_nt(const KDims& d, const KTab& t, const KCoef& c, const StageA
   const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
   const bool an = d.scattering && c.aniso && a.mode != PM_APPLY;
   if constexpr (sizeof(TY) == 8 && sizeof(TO) == 8) {
+    if (na && ny && a.accsrc == a.ysrc) {  // y is the accumulator source: load it once (AB2 step 3 % faster)
+      if (an) launch_plane_t<NT, true, 4, TY, TO, TC, true>(d, t, c, a, s);
+      else launch_plane_t<NT, true, 4, TY, TO, TC, false>(d, t, c, a, s);
+      return;
+    }
     if (a.accrec) {  // checked by launch_plane: ysrc given, no accumulator source
       if (an) launch_plane_t<NT, false, 2, TY, TO, TC, true>(d, t, c, a, s);
       else launch_plane_t<NT, false, 2, TY, TO, TC, false>(d, t, c, a, s);
