@@ -1,10 +1,12 @@
 // Plane passes: everything that needs a whole (Theta, Phi) plane.
 //
-// A workgroup stages NPW planes in LDS.  Each lane of a wavefront owns one line
-// of length L = 2 n_Theta = n_Phi: either a Theta DFS line (column Phi_m followed
-// by the reversed column Phi_m + pi, since the direction (-Theta, Phi) is
-// (Theta, Phi + pi)) or a Phi row; the wavefronts split the output pairs of every
-// line.  Forward (Eq. Liouvsph): Theta term -(sin Theta / r) dF/dTheta, Phi term
+// A workgroup stages NPW planes in LDS.  The lines have length L = 2 n_Theta =
+// n_Phi: a Theta DFS line (column Phi_m followed by the reversed column
+// Phi_m + pi, since the direction (-Theta, Phi) is (Theta, Phi + pi)) or a Phi
+// row.  On 16 x 32 planes the even and odd halves of both line operators run as
+// 16 x 16 x 16 MFMA products (one direction of one plane per wavefront); on the
+// other plane shapes each lane owns one line and the wavefronts split its
+// output pairs.  Forward (Eq. Liouvsph): Theta term -(sin Theta / r) dF/dTheta, Phi term
 // -(sin Theta sin Phi cos theta / (r sin theta)) dF/dPhi.  The epilogue adds the
 // r/theta/phi terms produced by the column passes, the collision term
 // eta - (kappa + sigma) F + sigma <F> (Eq. Transp with an isotropic kernel,
