@@ -49,12 +49,13 @@ SP6_DEV int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 // global accesses carry the nontemporal hint (bits below).  Measured on the
 // 33 x 16 x 32 x 16 x 32 grid: on the loads and stores of the plane pass it takes
 // the pass from 4.66 to 5.03 TB/s; on the radial pass's T loads and stores from
-// 4.84 to 5.0 TB/s (its stage-input loads keep the plain hint: that input is read
-// again by the plane pass, which finds it in the last-level cache); on the
-// theta-phi pass (partial-line stores) it costs 12 %, so that pass has none; the
-// adjoint plane pass streams all its operands with it.
+// 4.84 to 5.0 TB/s, and on its stage-input loads from 331 to 318 us (the next
+// plane pass, which reads that input again, loses 6 us of it; with the plane
+// lines streamed from LDS it had lost all of it); on the theta-phi pass
+// (partial-line stores) it costs 12 %, so that pass has none; the adjoint plane
+// pass streams all its operands with it.
 #ifndef SP6_NT
-#define SP6_NT 1995
+#define SP6_NT 1999
 #endif
 template <int BIT, typename T>
 SP6_DEV T ld_stream(const T* p) {
