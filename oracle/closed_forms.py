@@ -10,8 +10,6 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
   eta = kappa B: along each ray the stationary transport equation
   dI/ds = kappa (B - I) with I = 0 where the ray enters the sphere gives
   I = B (1 - exp(-kappa s)), s = r mu + sqrt(R_s^2 - r^2 (1 - mu^2)), mu = cos Theta.
-* B(eps, T) = 2 eps^2 / (exp(eps/T) - 1): the steady state of Eq. (Bose) at zero
-  chemical potential, in the same F = gamma^2 f normalisation (Sect. 3.2).
 * Isotropisation in a uniform scattering medium (the experiment of Sect. 5.2,
   with smooth data): a spatially uniform F(omega) has L F = 0, and the scattering
   term multiplies its spherical-harmonic part of degree l by -sigma (1 - lambda_l),
@@ -48,11 +46,6 @@ def on_grid(g, fn):
 def free_streaming(g, fn, t):
     """F(t) = F0(x - t omega, omega) on the nodes of g."""
     return on_grid(g, lambda x, y, z, ox, oy, oz: fn(x - t * ox, y - t * oy, z - t * oz, ox, oy, oz))
-
-
-def planck_like(eps, T):
-    """B(eps, T) = 2 eps^2 / (exp(eps / T) - 1)."""
-    return 2.0 * eps ** 2 / np.expm1(eps / T)
 
 
 def homogeneous_sphere(g, kappa, B, R_s):

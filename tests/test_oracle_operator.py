@@ -311,3 +311,67 @@ def test_project_inflow_sets_only_incoming_half():
         np.testing.assert_array_equal(P[:, 0, :, :, i], gi[:, :, :, i] if cT[i] > 0 else F[:, 0, :, :, i])
         np.testing.assert_array_equal(P[:, -1, :, :, i], go[:, :, :, i] if cT[i] < 0 else F[:, -1, :, :, i])
     np.testing.assert_array_equal(P[:, 1:-1], F[:, 1:-1])
+
+
+def test_outgoing_flux_map_against_boundary_flux():
+    # App. A, Eq. (Flux): for F that vanishes on the incoming half at r_out
+    # (cos Theta < 0), the flux map integrated over the position sphere with the
+    # same theta/phi weights is J_out / R2^2.  A map over the wrong hemisphere
+    # gives 0, one without the cos Theta weight a different sum.
+    g = og.make_grid(2, 7, 4, 8, 6, 12)
+    rng = np.random.default_rng(21)
+    F = rng.normal(size=g.shape)
+    cT = np.cos(g.Theta)
+    F[:, -1][:, :, :, cT < 0] = 0.0
+    j = diagnostics.outgoing_flux_map(F, g)
+    w_pos = g.w_theta[:, None] * np.full(g.n_phi, 2.0 * np.pi / g.n_phi)[None, :]
+    J_out = diagnostics.boundary_flux(F, g, g.n_r - 1)
+    got = np.sum(j * w_pos[None], axis=(1, 2))
+    np.testing.assert_allclose(got, J_out / g.r_out ** 2, rtol=1e-13)
+
+
+def test_outgoing_flux_map_closed_form():
+    # F = cos(Theta) g(theta, phi) at r_out: the half-range sum of w_i cos^2 Theta_i
+    # is half the full one (the half-shifted nodes are symmetric about pi/2), and
+    # Fejer's rule integrates mu^2 exactly: (1/2)(2/3); the trapezoid sum over Phi
+    # gives 2 pi.  So j = (2 pi / 3) g(theta, phi) for every position node.
+    g = og.make_grid(1, 5, 4, 8, 8, 16)
+    r, th, ph, Th, Ph = g.mesh()
+    gpos = 1.0 + 0.3 * np.cos(th) + 0.2 * np.sin(th) * np.sin(ph)
+    F = np.broadcast_to(np.cos(Th) * gpos + 0.0 * Ph + 0.0 * r, g.shape).copy()
+    j = diagnostics.outgoing_flux_map(F, g)
+    want = (2.0 * np.pi / 3.0) * np.broadcast_to(gpos, (1, 1, g.n_theta, g.n_phi, 1, 1))[:, 0, :, :, 0, 0]
+    np.testing.assert_allclose(j, want, rtol=1e-14)
+    # the transpose is exact against the map (dot-product test)
+    jbar = np.random.default_rng(3).normal(size=j.shape)
+    X = np.random.default_rng(4).normal(size=g.shape)
+    assert np.sum(diagnostics.outgoing_flux_map(X, g) * jbar) == pytest.approx(
+        np.sum(X * diagnostics.outgoing_flux_map_T(jbar, g)), rel=1e-13)
+
+
+def test_L_angular_of_paper_uniform_distribution_vanishes(g1):
+    # Eq. (propf): F(omega) does not depend on position, so L F = 0 and, as F has
+    # no r dependence in these coordinates, the angular part alone vanishes too.
+    c = _paper_value("uniform_test_coeffs")
+    F = cf.on_grid(g1, lambda x, y, z, ox, oy, oz: (c[0] + c[1] * ox + c[2] * oy + c[3] * oz) ** 4)
+    assert np.max(np.abs(ops.apply_L_angular(F, g1))) <= 1e-12 * np.max(np.abs(F))
+
+
+def test_L_angular_plus_radial_is_L():
+    # on unstructured data: the angular part plus cos(Theta) D_r F is the whole
+    # operator of Eq. (Liouvsph) (pinned above by Eqs. prop1/prop2/propf and
+    # brute force); and for F = x_i (no omega dependence) the angular part is
+    # omega_i - cos(Theta) dx_i/dr
+    g = og.make_grid(2, 9, 4, 8, 4, 8)
+    F = np.random.default_rng(22).normal(size=g.shape)
+    c_r = ops.liouville_coefficients(g)[0]
+    np.testing.assert_allclose(ops.apply_L_angular(F, g) + c_r * ops.d_r(F, g), ops.apply_L(F, g),
+                               rtol=0, atol=1e-12 * np.max(np.abs(ops.apply_L(F, g))))
+    gq = og.make_grid(1, 9, 8, 16, 8, 16)
+    r, th, ph, Th, Ph = gq.mesh()
+    for comp in range(3):
+        F = cf.on_grid(gq, lambda x, y, z, ox, oy, oz: (x, y, z)[comp])
+        om = cf.on_grid(gq, lambda x, y, z, ox, oy, oz: (ox, oy, oz)[comp])
+        # d x_i / dr = x_i / r on the ray of fixed (theta, phi)
+        want = om - np.cos(Th) * F / r
+        assert nrm(ops.apply_L_angular(F, gq), want) <= 1e-13
