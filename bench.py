@@ -1,25 +1,34 @@
 """Benchmark of the 6D spectral transport hot path on one MI355X.
 
-Headline workload: emission + absorption, 8 energy groups,
-(n_r, n_theta, n_phi, n_Theta, n_Phi) = (33, 16, 32, 16, 32): 69,206,016 points,
-FP64, classical RK4 at dt = 0.2 (r_1 - r_0).  One "step" is one full RK4 step over
-the whole grid; value = grid-point updates per second with every input already
-resident in HBM.  Inputs are synthetic and seeded (no dataset is involved).
+Headline workload: the large scattering workload, 4 energy groups,
+(n_r, n_theta, n_phi, n_Theta, n_Phi) = (65, 32, 64, 32, 64): 1,090,519,040 points
+(8.7 GB per FP64 state), emission + absorption + isotropic scattering
+sigma = kappa / 2, FP64, classical RK4 at dt = 0.2 (r_1 - r_0).  One "step" is one
+full RK4 step over the whole grid; value = grid-point updates per second with
+every input already resident in HBM.  Inputs are synthetic and seeded (no
+dataset is involved).
 
 Also measured on the same JSON line ("forms"):
-  mixed   : the scattering workload (same grid, sigma = kappa/2) on the mixed path,
-            with its error against the FP64 path after the timed steps;
-  large   : the 1.09e9-point scattering workload, FP64 and mixed;
-  implicit: the headline workload with the split step of App. B (backward-Euler
-            radial solve after RK4 on the other terms);
-  adjoint : the 4-group workload (same angular grid), 200 steps forward plus the
-            checkpointed (every 20) discrete-adjoint backward pass of the
+  large_mixed: the headline workload on the mixed path, with its error against
+            the FP64 path after the same steps;
+  w2_fp64 : emission + absorption, 8 groups on (33, 16, 32, 16, 32), FP64;
+  mixed   : that grid with sigma = kappa/2 on the mixed path, with its error
+            against the FP64 path after the timed steps;
+  thomson, shell, ab2, implicit: the anisotropic kernel, the 5D shell problem,
+            the paper's Adams-Bashforth integrator, the split step of App. B;
+  adjoint : the 4-group workload (same angular grid as w2), 200 steps forward
+            plus the checkpointed (every 20) discrete-adjoint backward pass of the
             outgoing-flux misfit; value = forward-equivalent updates (points x 200)
             over the forward + recompute + backward wall time.
 
-The roofline object is for the dominant kernel of the headline form: algorithmic
-bytes per launch (bytes per point below x points) over its mean HIP-event
-duration, against 8 TB/s.
+The roofline object is for the dominant kernel of the headline form (the plane
+pass): achieved = algorithmic bytes per launch over its mean HIP-event
+duration, against 8 TB/s.  The algorithmic bytes are the method's: a fully fused
+RK4 step moves 128 B per point (read the stage state, y and the accumulator as
+the scheme needs them, write the next ones), i.e. 32 B per point per stage, and
+one plane-pass launch is one stage over every point; the kernel's own bytes
+(36 B per point on average, T and the stage input included) are reported beside
+it.
 """
 
 import argparse
@@ -55,22 +64,24 @@ BYTES_MIXED = {"thetaphi": 9.0, "phi": 9.0, "theta": 13.0, "radial": 13.0, "plan
 # minimal traffic of a fully fused RK4 step (read the stage state once; y, acc and
 # the next stage state as registers of the scheme): 128 B (FP64), 104 B (mixed)
 FUSED_MIN_B = {"fp64": 128.0, "mixed": 104.0}
+# per plane-pass launch (one RK stage over every point): 128 / 4
+METHOD_B_PER_STAGE = {"fp64": 32.0, "mixed": 26.0}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["all", "fp64", "mixed", "large", "thomson", "shell", "ab2", "implicit", "adjoint"], default="all")
+    ap.add_argument("--form", choices=["all", "large", "fp64", "mixed", "thomson", "shell", "ab2", "implicit", "adjoint"],
+                    default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 553,648,128 bytes (byte-counter calibration)")
     return ap.parse_args()
 
 
-PROFILE_FP64 = os.path.join(ROOT, "profiles", "fp64_step_emit_abs_33x16x32x16x32_g8.md")
+PROFILE_FP64 = os.path.join(ROOT, "profiles", "fp64_step_scatter_65x32x64x32x64_g4.md")
 PLANE_SRC = os.path.join(ROOT, "paper_1104_5330_amd", "csrc", "k_plane.hip")
 
 
@@ -130,14 +141,47 @@ def run_steps(cfg, precision, scattering, steps, warmup, F0=None, kernel=None):
     return F, F0, ms, kt
 
 
-def form_fp64(args):
+def form_w2_fp64(args):
+    """Emission + absorption, 8 groups on (33, 16, 32, 16, 32), FP64."""
     import synth
     cfg = synth.config(2)
     _, _, ms, kt = run_steps(cfg, "fp64", False, args.steps, args.warmup)
     P = cfg.points
     value = P * args.steps / (ms / 1e3)
-    kern = kernel_table(kt, P, BYTES_FP64, ms)
-    return cfg, value, ms, kern
+    return {"workload": cfg.name, "grid": list(cfg.shape), "physics": "emission+absorption",
+            "value": value, "unit": "grid-point updates/s", "ms_per_step": ms / args.steps,
+            "steps": args.steps, "dtype": "f64", "kernels": kernel_table(kt, P, BYTES_FP64, ms),
+            "hbm_fraction_algorithmic_128B": value * FUSED_MIN_B["fp64"] / (HBM_PEAK_GBS * 1e9)}
+
+
+def form_large(args):
+    """The headline: the large scattering workload (4 groups, (65, 32, 64, 32, 64):
+    1.09e9 points, 8.7 GB per FP64 array) in FP64, then on the mixed path from the
+    same initial state, with the mixed path's error against the FP64 result."""
+    import torch
+    import synth
+    cfg = synth.config(5)
+    # 8.7 GB arrays: hand earlier cached blocks back first, so that the new
+    # arrays are mapped afresh
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    F64, F0, ms, kt = run_steps(cfg, "fp64", True, args.steps, args.warmup)
+    Fm, _, ms_m, kt_m = run_steps(cfg, "mixed", True, args.steps, args.warmup, F0=F0)
+    del F0
+    err_max = ((Fm - F64).abs().max() / F64.abs().max()).item()
+    err_l2 = (torch.linalg.vector_norm(Fm - F64) / torch.linalg.vector_norm(F64)).item()
+    del Fm, F64
+    torch.cuda.empty_cache()
+    P = cfg.points
+    value = P * args.steps / (ms / 1e3)
+    value_m = P * args.steps / (ms_m / 1e3)
+    mixed = {"workload": cfg.name, "grid": list(cfg.shape), "value": value_m, "unit": "grid-point updates/s",
+             "ms_per_step": ms_m / args.steps, "steps": args.steps,
+             "dtype": "f32 derivatives / bf16x3 MFMA radial / f64 state",
+             "kernels": kernel_table(kt_m, P, BYTES_MIXED, ms_m),
+             "error_vs_fp64": {"max_rel": err_max, "l2_rel": err_l2, "after_steps": args.steps},
+             "hbm_fraction_algorithmic_104B": value_m * FUSED_MIN_B["mixed"] / (HBM_PEAK_GBS * 1e9)}
+    return cfg, value, ms, kernel_table(kt, P, BYTES_FP64, ms), mixed
 
 
 def form_mixed(args):
@@ -157,37 +201,6 @@ def form_mixed(args):
         "error_vs_fp64": {"max_rel": err_max, "l2_rel": err_l2, "after_steps": args.steps},
         "hbm_fraction_algorithmic_104B": P * args.steps / (ms / 1e3) * FUSED_MIN_B["mixed"] / (HBM_PEAK_GBS * 1e9),
         "kernels": kernel_table(kt, P, BYTES_MIXED, ms),
-    }
-
-
-def form_large(args):
-    """The large scattering workload (4 groups, (65, 32, 64, 32, 64): 1.09e9 points,
-    8.7 GB per FP64 array), FP64 and mixed, a few steps each: theta lines of 64
-    points (separate theta and phi passes), 2048-point planes."""
-    import torch
-    import synth
-    cfg = synth.config(5)
-    steps = max(1, min(args.steps, 10))
-    # 8.7 GB arrays: hand the earlier forms' cached blocks back first, so that the
-    # new arrays are mapped afresh (the strided theta pass is sensitive to it)
-    torch.cuda.synchronize()
-    torch.cuda.empty_cache()
-    Fm, F0, ms_m, kt_m = run_steps(cfg, "mixed", True, steps, 1)
-    F64, _, ms, kt = run_steps(cfg, "fp64", True, steps, 1, F0=F0)
-    del F0
-    err_max = ((Fm - F64).abs().max() / F64.abs().max()).item()
-    err_l2 = (torch.linalg.vector_norm(Fm - F64) / torch.linalg.vector_norm(F64)).item()
-    P = cfg.points
-    # the separate theta pass reads Y and T and writes T (24 B), the phi pass 16 B
-    return {
-        "workload": cfg.name, "grid": list(cfg.shape), "points": P, "steps": steps,
-        "physics": "emission+absorption+isotropic scattering",
-        "fp64": {"value": P * steps / (ms / 1e3), "ms_per_step": ms / steps,
-                 "kernels": kernel_table(kt, P, BYTES_FP64, ms)},
-        "mixed": {"value": P * steps / (ms_m / 1e3), "ms_per_step": ms_m / steps,
-                  "kernels": kernel_table(kt_m, P, BYTES_MIXED, ms_m),
-                  "error_vs_fp64": {"max_rel": err_max, "l2_rel": err_l2, "after_steps": steps}},
-        "unit": "grid-point updates/s",
     }
 
 
@@ -358,19 +371,41 @@ def form_adjoint(args):
     }
 
 
-def cpu_baseline(nsteps):
-    """The oracle as it stands, timed on the host: nsteps RK4 steps of one energy
-    group of the headline workload (the groups are independent)."""
+def host_cpu():
+    """Model name and logical CPU count of the host (lscpu), as far as available."""
+    import subprocess
+    info = {"os_cpu_count": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Socket(s)"):
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        info["affinity_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        pass
+    return info
+
+
+def cpu_baseline():
+    """The oracle as it stands, timed on the host: the first of the four stages of
+    an RK4 step (one right-hand side and the stage update Y2 = y + dt/2 k1, as
+    step.rk4_stages forms them) of one energy group of the headline workload.  The
+    groups are independent and the four stages cost the same, so
+    updates/s = points / (4 t_stage)."""
     import numpy as np
     import synth
     from oracle import grid as og, step
 
-    cfg = synth.config(2)
+    cfg = synth.config(5)
     sub = cfg.scaled(n_eps=1)
+    k, s, e = (np.ascontiguousarray(a[-1:]) for a in synth.fields.coefficients(cfg))
     F = synth.fields.shell_state(sub)
-    k, s, e = synth.fields.coefficients(sub)
     g = og.make_grid(*sub.shape)
-    p = step.Physics(k, s, e, scattering=False)
+    p = step.Physics(k, s, e, scattering=True)
     threads = None
     try:
         from threadpoolctl import threadpool_info
@@ -378,15 +413,16 @@ def cpu_baseline(nsteps):
     except Exception:
         pass
     t0 = time.perf_counter()
-    y = F
-    for _ in range(nsteps):
-        y = step.rk4_step(y, g, p, sub.dt)
-    t = time.perf_counter() - t0
-    assert np.isfinite(y).all()
-    return {"value": sub.points * nsteps / t, "unit": "grid-point updates/s", "cores": threads or os.cpu_count(),
-            "kind": "oracle",
-            "sample": f"{nsteps} RK4 steps of 1 of {cfg.n_eps} energy groups ({sub.points} points) of the "
-                      f"headline workload, dense 1D matrices in numpy FP64, {t:.1f} s"}
+    k1 = step.rhs(F, g, p)
+    Y2 = F + 0.5 * cfg.dt * k1
+    t_stage = time.perf_counter() - t0
+    assert np.isfinite(Y2).all()
+    del Y2, k1, F
+    return {"value": sub.points / (4.0 * t_stage), "unit": "grid-point updates/s",
+            "cores": threads or os.cpu_count(), "kind": "oracle", "host": host_cpu(),
+            "sample": f"the first RK4 stage (right-hand side and stage update) of 1 of {cfg.n_eps} energy groups "
+                      f"({sub.points} points) of the headline workload in {t_stage:.1f} s; a step counted as four "
+                      f"such stages; dense 1D matrices in numpy FP64"}
 
 
 def copy_calibration():
@@ -409,28 +445,33 @@ def main():
     torch.cuda.set_device(0)
     out = {"metric": METRIC}
     forms = {}
-    if args.form in ("all", "fp64"):
-        cfg, value, ms, kern = form_fp64(args)
-        dom = max(kern, key=lambda c: kern[c]["avg_ms"] * kern[c]["launches"])
-        dk = kern[dom]
+    if args.form in ("all", "large"):
+        cfg, value, ms, kern, mixed = form_large(args)
+        dk = kern["plane"]
+        plane_s = dk["avg_ms"] / 1e3
+        achieved = METHOD_B_PER_STAGE["fp64"] * cfg.points / plane_s / 1e9
+        own = BYTES_FP64["plane"] * cfg.points / plane_s / 1e9
         out.update({
             "value": value, "unit": "grid-point updates/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": cfg.name, "grid": list(cfg.shape), "points": cfg.points,
-                       "physics": "emission+absorption", "dt": cfg.dt, "form": "fp64"},
-            "roofline": {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBs"], "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": dk["alg_GBs"] / HBM_PEAK_GBS,
-                         "traffic": measured_traffic() if dom == "plane" else None,
-                         "bytes_per_point_per_launch": BYTES_FP64[dom], "points_per_launch": cfg.points},
+                       "physics": "emission+absorption+isotropic scattering", "dt": cfg.dt, "form": "fp64"},
+            "roofline": {"bound": "hbm", "kernel": "plane", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(),
+                         "bytes_per_point_per_launch": METHOD_B_PER_STAGE["fp64"], "points_per_launch": cfg.points,
+                         "avg_launch_ms": dk["avg_ms"],
+                         "kernel_bytes_per_point_per_launch": BYTES_FP64["plane"],
+                         "achieved_kernel_bytes": own, "frac_kernel_bytes": own / HBM_PEAK_GBS},
             "kernels": kern,
             "hbm_fraction_algorithmic_128B": value * FUSED_MIN_B["fp64"] / (HBM_PEAK_GBS * 1e9),
         })
-        forms["fp64"] = {"value": value, "ms_per_step": ms / args.steps}
+        forms["large_mixed"] = mixed
+    if args.form in ("all", "fp64"):
+        forms["w2_fp64"] = form_w2_fp64(args)
     if args.form in ("all", "mixed"):
         forms["mixed"] = form_mixed(args)
-    if args.form in ("all", "large"):
-        forms["large"] = form_large(args)
     if args.form in ("all", "thomson"):
         forms["thomson"] = form_thomson(args)
     if args.form in ("all", "shell"):
@@ -444,8 +485,8 @@ def main():
     out["forms"] = forms
     if args.copy_calibration:
         out["copy_calibration"] = copy_calibration()
-    if not args.no_cpu_baseline and args.form in ("all", "fp64"):
-        out["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    if not args.no_cpu_baseline and args.form in ("all", "large"):
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -5,7 +5,8 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 * omega(theta, phi, Theta, Phi): the Cartesian components of the direction,
   Eqs. (omegax)-(omegaz), Sect. 4.1.
 * Free streaming: particles travel in straight lines between collisions
-  (Sect. 2.1), so with c = 1 and no collisions F(t, x, omega) = F0(x - t omega, omega).
+  (Sect. 2.1), so with c = 1 and no collisions F(t, x, omega) = F0(x - t omega, omega);
+  in the shell with zero inflow, zero where that segment crosses a boundary.
 * Homogeneous emitting/absorbing sphere of radius R_s with uniform kappa and
   eta = kappa B: along each ray the stationary transport equation
   dI/ds = kappa (B - I) with I = 0 where the ray enters the sphere gives
@@ -46,6 +47,24 @@ def on_grid(g, fn):
 def free_streaming(g, fn, t):
     """F(t) = F0(x - t omega, omega) on the nodes of g."""
     return on_grid(g, lambda x, y, z, ox, oy, oz: fn(x - t * ox, y - t * oy, z - t * oz, ox, oy, oz))
+
+
+def free_streaming_shell(g, fn, t):
+    """Free streaming in the shell r_in <= |x| <= r_out with zero inflow: the
+    particle at (x, omega) at time t came from x - t omega if the straight segment
+    x - s omega, 0 <= s <= t, stays inside the shell (Sect. 2.1), else it entered
+    through a boundary, where the inflow is zero (Sect. 4.2).  |x - s omega|^2 is
+    convex in s, so the segment leaves through r_out only if its start does, and
+    through r_in if its smallest radius, at s = clip(x . omega, 0, t), is below
+    r_in."""
+    def f(x, y, z, ox, oy, oz):
+        sx, sy, sz = x - t * ox, y - t * oy, z - t * oz
+        s_min = np.clip(x * ox + y * oy + z * oz, 0.0, t)
+        r_min2 = (x - s_min * ox) ** 2 + (y - s_min * oy) ** 2 + (z - s_min * oz) ** 2
+        inside = (sx * sx + sy * sy + sz * sz <= g.r_out ** 2) & (r_min2 >= g.r_in ** 2)
+        return np.where(inside, fn(sx, sy, sz, ox, oy, oz), 0.0)
+
+    return on_grid(g, f)
 
 
 def homogeneous_sphere(g, kappa, B, R_s):

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "range_check.h"
 #include "sp6_internal.h"
 
 hipError_t launch_filter_columns(const KDims& d, const KTab& t, double* F, hipStream_t s);
@@ -135,7 +136,11 @@ sp6_status check_grid(sp6_grid g) {
   return SP6_OK;
 }
 
-// A device array of `bytes` bytes: non-null, 16-byte aligned, device memory.
+// A device array of `bytes` bytes: non-null, 16-byte aligned, device memory, and
+// [p, p + bytes) inside the one device allocation that contains p.  (A caching
+// allocator hands out parts of larger allocations, so a buffer that is too
+// short but followed by more of its allocation is not detected; one that runs
+// past the allocation's end is.)
 sp6_status check_dev(const void* p, size_t bytes, const char* name) {
   if (!p) return fail(SP6_ERR_ARG, std::string(name) + " is NULL");
   if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(SP6_ERR_ARG, std::string(name) + " is not 16-byte aligned");
@@ -148,7 +153,16 @@ sp6_status check_dev(const void* p, size_t bytes, const char* name) {
   }
   if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged && attr.type != hipMemoryTypeUnified)
     return fail(SP6_ERR_ARG, std::string(name) + " is not device memory");
-  (void)bytes;
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SP6_ERR_ARG, std::string(name) + ": the device allocation holding it could not be found");
+  }
+  if (!sp6_range_inside(reinterpret_cast<uintptr_t>(base), size, reinterpret_cast<uintptr_t>(p), bytes))
+    return fail(SP6_ERR_ARG, std::string(name) + " is too small: " + std::to_string(bytes) +
+                                 " bytes from it run past the end of its device allocation");
   return SP6_OK;
 }
 
@@ -200,31 +214,32 @@ hipError_t ensure_step_scratch(sp6_grid g) {
 
 // the r, theta and phi terms of L Y (or of L^T for the transposed passes) into T
 hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transpose, bool mask_in,
-                        double in_scale, bool* wrote, Timer* tm = nullptr) {
+                        double in_scale, bool* wrote, Timer* tm = nullptr, double* Tdst = nullptr) {
   hipError_t e = hipSuccess;
   bool acc = false;
   const double sg = transpose ? -1.0 : 1.0;
+  double* T = Tdst ? Tdst : g->T;
   if ((terms & 6u) == 6u && sphere_fusable(g->d, false)) {
-    e = launch_sphere(next_pass(g), g->t, Y, g->T, sg, mask_in, in_scale, g->stream);
+    e = launch_sphere(next_pass(g), g->t, Y, T, sg, mask_in, in_scale, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
     if (e != hipSuccess) return e;
     acc = true;
     terms &= ~6u;
   }
   if (terms & 4u) {
-    e = launch_phi(g->d, g->t, Y, g->T, acc, sg, mask_in, in_scale, g->stream);
+    e = launch_phi(g->d, g->t, Y, T, acc, sg, mask_in, in_scale, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_PHI);
     if (e != hipSuccess) return e;
     acc = true;
   }
   if (terms & 2u) {
-    e = launch_theta(g->d, g->t, Y, g->T, acc, sg, mask_in, in_scale, g->stream);
+    e = launch_theta(g->d, g->t, Y, T, acc, sg, mask_in, in_scale, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_THETA);
     if (e != hipSuccess) return e;
     acc = true;
   }
   if (terms & 1u) {
-    e = launch_radial(next_pass(g), g->t, Y, g->T, acc, transpose, mask_in, in_scale, g->stream);
+    e = launch_radial(next_pass(g), g->t, Y, T, acc, transpose, mask_in, in_scale, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_RADIAL);
     if (e != hipSuccess) return e;
     acc = true;
@@ -235,30 +250,31 @@ hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transp
 
 // mixed path: the r, theta and phi terms of L Y in FP32 (Y stored in FP64 or FP32)
 hipError_t column_terms_mixed(sp6_grid g, const void* Y, bool y_f32, uint32_t terms, bool* wrote,
-                              Timer* tm = nullptr) {
+                              Timer* tm = nullptr, float* Tdst = nullptr) {
   hipError_t e = hipSuccess;
   bool acc = false;
+  float* Tf = Tdst ? Tdst : g->Tf;
   if ((terms & 6u) == 6u && sphere_fusable(g->d, true)) {
-    e = launch_sphere_mixed(next_pass(g), g->t, Y, y_f32, g->Tf, g->stream);
+    e = launch_sphere_mixed(next_pass(g), g->t, Y, y_f32, Tf, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
     if (e != hipSuccess) return e;
     acc = true;
     terms &= ~6u;
   }
   if (terms & 4u) {
-    e = launch_phi_mixed(g->d, g->t, Y, y_f32, g->Tf, acc, g->stream);
+    e = launch_phi_mixed(g->d, g->t, Y, y_f32, Tf, acc, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_PHI);
     if (e != hipSuccess) return e;
     acc = true;
   }
   if (terms & 2u) {
-    e = launch_theta_mixed(g->d, g->t, Y, y_f32, g->Tf, acc, g->stream);
+    e = launch_theta_mixed(g->d, g->t, Y, y_f32, Tf, acc, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_THETA);
     if (e != hipSuccess) return e;
     acc = true;
   }
   if (terms & 1u) {
-    e = launch_radial_bf16x3(next_pass(g), g->t, Y, y_f32, g->Tf, acc, g->stream);
+    e = launch_radial_bf16x3(next_pass(g), g->t, Y, y_f32, Tf, acc, g->stream);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_RADIAL);
     if (e != hipSuccess) return e;
     acc = true;
@@ -304,8 +320,18 @@ sp6_status check_state_io(sp6_grid g, const void* in, const char* nin, const voi
   return check_distinct(in, nin, out, nout, B, B);
 }
 
+// Scratch of the RK4 step: T and (FP64 path) the stage buffer and accumulator,
+// or (mixed path) the FP32 stage copy and T plus the FP64 accumulator
+struct StepBufs {
+  double* T = nullptr;
+  double* Y = nullptr;
+  double* acc = nullptr;
+  float* Yf = nullptr;
+  float* Tf = nullptr;
+};
+
 sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit = false,
-                     double* Ystages = nullptr);
+                     double* Ystages = nullptr, const StepBufs* given = nullptr);
 
 }  // namespace
 
@@ -621,7 +647,7 @@ sp6_status ensure_radial_implicit(sp6_grid g, double dt) {
 // Ystages (one step, FP64): the stage inputs Y2, Y3, Y4 are written there, back
 // to back, instead of into the handle's stage buffer
 sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm, bool radial_implicit,
-                     double* Ystages) {
+                     double* Ystages, const StepBufs* given) {
   if (sp6_status s = check_grid(g)) return s;
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
@@ -630,12 +656,18 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
   if (nsteps == 0) return SP6_OK;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   const bool mixed = g->desc.precision == SP6_MIXED;
-  if (mixed) {
-    HIP_TRY(ensure_f32(g, &g->Yf), "allocate scratch");
-    HIP_TRY(ensure_f32(g, &g->Tf), "allocate scratch");
-    HIP_TRY(ensure(g, &g->acc, state_bytes(g)), "allocate scratch");
+  StepBufs b;
+  if (given) {
+    b = *given;
   } else {
-    HIP_TRY(ensure_step_scratch(g), "allocate scratch");
+    if (mixed) {
+      HIP_TRY(ensure_f32(g, &g->Yf), "allocate scratch");
+      HIP_TRY(ensure_f32(g, &g->Tf), "allocate scratch");
+      HIP_TRY(ensure(g, &g->acc, state_bytes(g)), "allocate scratch");
+    } else {
+      HIP_TRY(ensure_step_scratch(g), "allocate scratch");
+    }
+    b.T = g->T, b.Y = g->Ybuf, b.acc = g->acc, b.Yf = g->Yf, b.Tf = g->Tf;
   }
   if (radial_implicit)
     if (sp6_status st = ensure_radial_implicit(g, dt)) return st;
@@ -651,38 +683,38 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
       a.mixed = mixed;
       if (mixed) {
         // stage 1 reads the FP64 state; later stages the FP32 stage copy
-        const void* Yin = (s == 1) ? static_cast<const void*>(F) : static_cast<const void*>(g->Yf);
-        HIP_TRY(column_terms_mixed(g, Yin, s != 1, cols, &wrote, tm), "column passes");
+        const void* Yin = (s == 1) ? static_cast<const void*>(F) : static_cast<const void*>(b.Yf);
+        HIP_TRY(column_terms_mixed(g, Yin, s != 1, cols, &wrote, tm, b.Tf), "column passes");
         a.Yin = Yin;
         a.yin_f32 = s != 1;
-        a.T = g->Tf;
+        a.T = b.Tf;
       } else {
-        const double* Yin = (s == 1) ? F : (Ystages ? Ystages + size_t(s - 2) * size_t(d.P) : g->Ybuf);
-        HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm), "column passes");
+        const double* Yin = (s == 1) ? F : (Ystages ? Ystages + size_t(s - 2) * size_t(d.P) : b.Y);
+        HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm, b.T), "column passes");
         a.Yin = Yin;
-        a.T = g->T;
+        a.T = b.T;
       }
-      void* ybuf = mixed ? static_cast<void*>(g->Yf) : static_cast<void*>(g->Ybuf);
+      void* ybuf = mixed ? static_cast<void*>(b.Yf) : static_cast<void*>(b.Y);
       if (Ystages && s <= 3) ybuf = Ystages + size_t(s - 1) * size_t(d.P);
       switch (s) {
         case 1:
-          a.accsrc = nullptr, a.accdst = g->acc, a.cb = dt / 6.0;
+          a.accsrc = nullptr, a.accdst = b.acc, a.cb = dt / 6.0;
           a.ysrc = nullptr, a.ynext = ybuf, a.cn = 0.5 * dt;
           // FP64: the accumulator is first written in stage 2, from F and
           // Y2 = F + dt/2 k1 (8 of 32 bytes per point)
           if (!mixed) a.accdst = nullptr;
           break;
         case 2:
-          a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
+          a.accsrc = b.acc, a.accdst = b.acc, a.cb = dt / 3.0;
           a.ysrc = F, a.ynext = ybuf, a.cn = 0.5 * dt;
           if (!mixed) a.accsrc = nullptr, a.accrec = 1;
           break;
         case 3:
-          a.accsrc = g->acc, a.accdst = g->acc, a.cb = dt / 3.0;
+          a.accsrc = b.acc, a.accdst = b.acc, a.cb = dt / 3.0;
           a.ysrc = F, a.ynext = ybuf, a.cn = dt;
           break;
         default:
-          a.accsrc = g->acc, a.accdst = F, a.cb = dt / 6.0;
+          a.accsrc = b.acc, a.accdst = F, a.cb = dt / 6.0;
           a.ysrc = nullptr, a.ynext = nullptr, a.cn = 0.0;
           break;
       }

@@ -77,41 +77,65 @@ def _broadcast_eps(cfg, f5):
 # initial states
 
 
-def beam(cfg, seed=0, width=0.5, noise=1e-3):
-    """Gaussian beam exp(-|x - x_c|^2 / (2 w^2)) times the clipped lobe
-    max(0, omega . d)^4, plus `noise` times a random polynomial field normalised
-    to max |N| = 1.  x_c = 2 u with u uniform on the unit sphere (first draw of
-    default_rng(seed)); d = u (radially outward beam).  The noise field is
-    sum c T_a(xi(r)) xhat^alpha omega^beta over a <= 3, |alpha| <= 3,
-    |beta| <= 3 with c ~ N(0, 1) drawn in C order over [a][alpha][beta]."""
+def beam_function(cfg, seed=0, width=0.5, noise=1e-3):
+    """The initial state of the free-streaming workload as a function of the
+    Cartesian position and direction, f(x, y, z, ox, oy, oz) (numpy arrays that
+    broadcast together; positions anywhere with |x| > 0).
+
+    Gaussian beam exp(-|x - x_c|^2 / (2 w^2)) times the clipped lobe
+    max(0, omega . d)^4, plus `noise` times a random polynomial field N normalised
+    to max |N| = 1 over the grid nodes.  x_c = 2 u with u uniform on the unit
+    sphere (first draw of default_rng(seed)); d = u (radially outward beam).  N is
+    sum c T_a(xi(|x|)) xhat^alpha omega^beta over a <= 3, |alpha| <= 3,
+    |beta| <= 3, xhat = x / |x|, with c ~ N(0, 1) drawn in C order over
+    [a][alpha][beta]."""
     rng = np.random.default_rng(seed)
     u = rng.normal(size=3)
     u /= np.linalg.norm(u)
     xc = 2.0 * u
+    mons = _monomials(3)
+    c = rng.normal(size=(4, len(mons), len(mons)))
+
+    def noise_field(x, om):
+        r = np.sqrt(x[0] ** 2 + x[1] ** 2 + x[2] ** 2)
+        xh = [x[a] / r for a in range(3)]
+        xi = _xi(cfg, r)
+        xm = [xh[0] ** e[0] * xh[1] ** e[1] * xh[2] ** e[2] for e in mons]
+        om_m = [om[0] ** e[0] * om[1] ** e[1] * om[2] ** e[2] for e in mons]
+        N = 0.0
+        for a in range(4):
+            Ta = _cheb_T(a, xi)
+            inner = 0.0
+            for ia, xa in enumerate(xm):
+                s = 0.0
+                for ib, ob in enumerate(om_m):
+                    s = s + c[a, ia, ib] * ob
+                inner = inner + xa * s
+            N = N + Ta * inner
+        return N
+
+    r, th, ph, Th, Ph = _mesh5(cfg)
+    er, om = _cart(r, th, ph, Th, Ph)
+    nmax = np.max(np.abs(noise_field([r * er[a] for a in range(3)], om)))
+
+    def f(x, y, z, ox, oy, oz):
+        d2 = (x - xc[0]) ** 2 + (y - xc[1]) ** 2 + (z - xc[2]) ** 2
+        odot = ox * u[0] + oy * u[1] + oz * u[2]
+        F = np.exp(-d2 / (2.0 * width ** 2)) * np.maximum(0.0, odot) ** 4
+        return F + noise * noise_field((x, y, z), (ox, oy, oz)) / nmax
+
+    return f
+
+
+def beam(cfg, seed=0, width=0.5, noise=1e-3):
+    """beam_function sampled at the grid nodes (every energy group the same)."""
+    f = beam_function(cfg, seed, width, noise)
     r, th, ph, Th, Ph = _mesh5(cfg)
     er, om = _cart(r, th, ph, Th, Ph)
     x = [r * er[a] for a in range(3)]
-    d2 = sum((x[a] - xc[a]) ** 2 for a in range(3))
-    odot = sum(om[a] * u[a] for a in range(3))
-    F = np.exp(-d2 / (2.0 * width ** 2)) * np.maximum(0.0, odot) ** 4
-    mons = _monomials(3)
-    c = rng.normal(size=(4, len(mons), len(mons)))
-    xi = _xi(cfg, r)
-    xm = [er[0] ** e[0] * er[1] ** e[1] * er[2] ** e[2] for e in mons]
-    om_m = [om[0] ** e[0] * om[1] ** e[1] * om[2] ** e[2] for e in mons]
-    N = 0.0
-    for a in range(4):
-        Ta = _cheb_T(a, xi)
-        inner = 0.0
-        for ia, xa in enumerate(xm):
-            s = 0.0
-            for ib, ob in enumerate(om_m):
-                s = s + c[a, ia, ib] * ob
-            inner = inner + xa * s
-        N = N + Ta * inner
-    N = np.broadcast_to(N, F.shape)
-    F = F + noise * N / np.max(np.abs(N))
-    return _broadcast_eps(cfg, F)
+    F = f(x[0], x[1], x[2], om[0], om[1], om[2])
+    shp = np.broadcast_shapes(*(np.shape(v) for v in (r, th, ph, Th, Ph)))
+    return _broadcast_eps(cfg, np.broadcast_to(F, shp))
 
 
 def polynomial_state(cfg, seed=0, deg_x=2, deg_om=2, scale=1.0):

@@ -106,3 +106,37 @@ def test_product_path_does_not_import_oracle():
                 with open(os.path.join(dirpath, f)) as fh:
                     txt = fh.read()
                 assert "oracle" not in txt.lower() or f == "build.py", f
+
+
+def test_range_check_host_build(tmp_path, root):
+    # the bounds arithmetic of the host validation (csrc/range_check.h), built on
+    # its own with the host compiler: edges, wrap-around, zero sizes
+    src = tmp_path / "t.cpp"
+    src.write_text(r'''
+#include "range_check.h"
+#include <cstdio>
+#include <cstdint>
+int main() {
+  const uintptr_t B = 0x7f0000000000ull;
+  struct { uintptr_t base; size_t size; uintptr_t p; size_t bytes; bool want; } c[] = {
+    {B, 4096, B, 4096, true}, {B, 4096, B, 4097, false}, {B, 4096, B + 16, 4080, true},
+    {B, 4096, B + 16, 4081, false}, {B, 4096, B - 16, 16, false}, {B, 4096, B + 4096, 0, true},
+    {B, 4096, B + 4112, 0, false}, {B, 4096, B + 8, SIZE_MAX, false}, {B, 0, B, 0, true},
+    {B, 4096, UINTPTR_MAX - 8, 16, false}, {0, SIZE_MAX, 16, SIZE_MAX - 16, true},
+  };
+  int bad = 0;
+  for (auto& k : c) bad += sp6_range_inside(k.base, k.size, k.p, k.bytes) != k.want;
+  std::printf("%d\n", bad);
+  return bad;
+}
+''')
+    import shutil
+    import subprocess
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    inc = os.path.join(root, "paper_1104_5330_amd", "csrc")
+    exe = tmp_path / "t"
+    subprocess.run([cxx, "-std=c++17", "-O1", "-Wall", "-I", inc, str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout

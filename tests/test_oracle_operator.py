@@ -375,3 +375,40 @@ def test_L_angular_plus_radial_is_L():
         # d x_i / dr = x_i / r on the ray of fixed (theta, phi)
         want = om - np.cos(Th) * F / r
         assert nrm(ops.apply_L_angular(F, gq), want) <= 1e-13
+
+
+def test_free_streaming_shell_brute_force():
+    # the inside/outside decision of the shell closed form against a brute-force
+    # walk along each backward segment (2001 points)
+    g = og.make_grid(1, 5, 4, 8, 4, 8)
+    t = 0.9
+    one = lambda x, y, z, ox, oy, oz: 1.0 + 0.0 * (x + ox)  # noqa: E731
+    got = cf.free_streaming_shell(g, one, t)
+    r, th, ph, Th, Ph = g.mesh()
+    X = np.broadcast_arrays(*cf.position(r, th, ph))
+    O = np.broadcast_arrays(*cf.omega(th, ph, Th, Ph))
+    shp = np.broadcast_shapes(X[0].shape, O[0].shape)
+    X = [np.broadcast_to(a, shp) for a in X]
+    O = [np.broadcast_to(a, shp) for a in O]
+    inside = np.ones(shp, bool)
+    for s in np.linspace(0.0, t, 2001):
+        rr = np.sqrt(sum((X[a] - s * O[a]) ** 2 for a in range(3)))
+        inside &= (rr >= g.r_in - 1e-12) & (rr <= g.r_out + 1e-12)
+    np.testing.assert_array_equal(got[0], np.where(inside, 1.0, 0.0)[0])
+    assert 0.2 < inside.mean() < 0.9  # both outcomes occur
+
+
+def test_config1_closed_form_report():
+    # Config 1 as specified (zero inflow, 10 steps): the oracle against
+    # F0(x - t omega, omega) in the shell.  Resolution limited (17 x 8 x 16 x 8 x 16
+    # for a w = 0.5 beam with a C^3 lobe): a report with a loose bound.
+    cfg = synth.config(1)
+    g = og.make_grid(*cfg.shape)
+    f0 = synth.fields.beam_function(cfg)
+    F = ops.project_inflow(synth.fields.beam(cfg), g)
+    y = step.run(F, g, step.Physics.vacuum(g), cfg.dt, cfg.steps)
+    want = cf.free_streaming_shell(g, f0, cfg.steps * cfg.dt)
+    mr = nrm(y, want)
+    l2 = np.linalg.norm((y - want).ravel()) / np.linalg.norm(want.ravel())
+    print(f"config 1 oracle vs closed form after {cfg.steps} steps: max-rel {mr:.3e} L2-rel {l2:.3e}")
+    assert l2 < 0.15 and mr < 0.3
