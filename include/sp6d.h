@@ -226,6 +226,23 @@ sp6_status sp6_outgoing_flux(sp6_grid grid, const double* F, double* j);
  * for cos(Theta_i) > 0 (and 0 otherwise).  jbar: device [n_eps][n_theta][n_phi]. */
 sp6_status sp6_outgoing_flux_T(sp6_grid grid, const double* jbar, double* out);
 
+/* Size of the fixed device scratch of sp6_step_noalloc, per GPU. */
+#define SP6_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* sp6_step without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture before a handle's first step, serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * sp6_step; the step's scratch (FP64: T, stage buffer and accumulator, 24 bytes
+ * per point; mixed: FP32 stage copy and T plus the FP64 accumulator, 16 bytes
+ * per point) lives in one fixed array of SP6_NOALLOC_SCRATCH_BYTES per GPU inside
+ * the library (looked up by sp6_create), so FP64 handles of up to 11,184,810
+ * points and mixed handles of up to 16,777,216 points are accepted; larger ones
+ * return SP6_ERR_SHAPE.  Every call on a GPU shares that GPU's array, which keeps
+ * the last call's contents (nothing in it needs to start at zero): calls that
+ * overlap on one GPU (other streams, other threads, other handles) race and
+ * must be serialised by the caller.  Needs coefficients. */
+sp6_status sp6_step_noalloc(sp6_grid grid, double* F, double dt, int32_t nsteps);
+
 /* Bytes of device memory the handle currently holds. */
 sp6_status sp6_device_bytes(sp6_grid grid, size_t* bytes);
 

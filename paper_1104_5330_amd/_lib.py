@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(_HERE, "libsp6d.so")
 
 SP6_OK, SP6_ERR_ARG, SP6_ERR_SHAPE, SP6_ERR_ALLOC, SP6_ERR_HIP, SP6_ERR_STATE = range(6)
 SP6_FP64, SP6_MIXED = 0, 1
+SP6_NOALLOC_SCRATCH_BYTES = 256 << 20
 STATUS_NAMES = {0: "SP6_OK", 1: "SP6_ERR_ARG", 2: "SP6_ERR_SHAPE", 3: "SP6_ERR_ALLOC", 4: "SP6_ERR_HIP",
                 5: "SP6_ERR_STATE"}
 
@@ -20,7 +21,7 @@ SYMBOLS = [
     "sp6_get_nodes", "sp6_get_weights", "sp6_set_coefficients", "sp6_set_scattering_kernel", "sp6_set_inflow",
     "sp6_project_inflow", "sp6_apply_L", "sp6_apply_L_terms", "sp6_apply_LT", "sp6_rhs",
     "sp6_step", "sp6_step_stages", "sp6_adjoint_step_stages", "sp6_step_radial_implicit", "sp6_step_ab2", "sp6_step_timed", "sp6_adjoint_step", "sp6_apply_filter", "sp6_diagnostics",
-    "sp6_outgoing_flux", "sp6_outgoing_flux_T", "sp6_device_bytes",
+    "sp6_outgoing_flux", "sp6_outgoing_flux_T", "sp6_step_noalloc", "sp6_device_bytes",
 ]
 
 
@@ -82,6 +83,7 @@ def load():
         "sp6_diagnostics": (S, [P, P, dp, dp, dp]),
         "sp6_outgoing_flux": (S, [P, P, P]),
         "sp6_outgoing_flux_T": (S, [P, P, P]),
+        "sp6_step_noalloc": (S, [P, P, D, I32]),
         "sp6_device_bytes": (S, [P, ctypes.POINTER(ctypes.c_size_t)]),
     }
     for name, (res, args) in sig.items():

@@ -73,6 +73,8 @@ struct sp6_grid_s {
   // the dt they were built for
   double* Bimp = nullptr;
   double imp_dt = 0.0;
+  // device address of the fixed scratch of sp6_step_noalloc on this device
+  void* noalloc = nullptr;
 
   hipError_t alloc(void** p, size_t n) {
     hipError_t e = hipMalloc(p, n);
@@ -404,6 +406,10 @@ sp6_status sp6_create(const sp6_desc* desc, void* hip_stream, sp6_grid* out) {
     return hip_fail(e, "hipDeviceGetAttribute");
   }
   if (d.ncu < 1) d.ncu = 1;
+  if ((e = noalloc_scratch_ptr(g->device, &g->noalloc)) != hipSuccess) {
+    delete g;
+    return hip_fail(e, "scratch address of sp6_step_noalloc");
+  }
 
   const HostTables& h = g->h;
   KTab& t = g->t;
@@ -738,6 +744,31 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
 extern "C" {
 
 sp6_status sp6_step(sp6_grid g, double* F, double dt, int32_t nsteps) { return run_steps(g, F, dt, nsteps, nullptr); }
+
+sp6_status sp6_step_noalloc(sp6_grid g, double* F, double dt, int32_t nsteps) {
+  if (sp6_status s = check_grid(g)) return s;
+  const bool mixed = g->desc.precision == SP6_MIXED;
+  const size_t P = size_t(g->d.P);
+  auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+  const size_t need = mixed ? 2 * up(4 * P) + up(8 * P) : 3 * up(8 * P);
+  if (need > SP6_NOALLOC_SCRATCH_BYTES)
+    return fail(SP6_ERR_SHAPE, "sp6_step_noalloc: the step needs " + std::to_string(need) +
+                                   " bytes of scratch, more than its fixed " +
+                                   std::to_string(size_t(SP6_NOALLOC_SCRATCH_BYTES)) + " bytes");
+  if (!g->noalloc) return fail(SP6_ERR_STATE, "sp6_step_noalloc: no scratch address on this device");
+  char* base = static_cast<char*>(g->noalloc);
+  StepBufs b;
+  if (mixed) {
+    b.Yf = reinterpret_cast<float*>(base);
+    b.Tf = reinterpret_cast<float*>(base + up(4 * P));
+    b.acc = reinterpret_cast<double*>(base + 2 * up(4 * P));
+  } else {
+    b.T = reinterpret_cast<double*>(base);
+    b.Y = reinterpret_cast<double*>(base + up(8 * P));
+    b.acc = reinterpret_cast<double*>(base + 2 * up(8 * P));
+  }
+  return run_steps(g, F, dt, nsteps, nullptr, false, nullptr, &b);
+}
 
 sp6_status sp6_step_stages(sp6_grid g, double* F, double dt, double* Ystages) {
   if (sp6_status s = check_grid(g)) return s;

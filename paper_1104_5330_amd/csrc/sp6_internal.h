@@ -12,6 +12,10 @@
 // largest supported n_r (descriptor validation; per-workgroup LDS tables)
 constexpr int SP6_MAX_NR = 80;
 
+// device address of the fixed scratch of sp6_step_noalloc (SP6_NOALLOC_SCRATCH_BYTES
+// bytes, 256-byte aligned) on `device`, the current device; cached per device
+hipError_t noalloc_scratch_ptr(int device, void** out);
+
 // ---------------------------------------------------------------------------
 // sizes and device tables, passed to kernels by value
 

@@ -154,6 +154,13 @@ class Sp6Grid:
         self._call(self.lib.sp6_step, _ptr(F, "F", self.shape), ctypes.c_double(dt), ctypes.c_int32(nsteps))
         return F
 
+    def step_noalloc(self, F, dt, nsteps=1):
+        """step() with its scratch in the library's fixed per-GPU array (no device
+        allocation; grids of up to SP6_NOALLOC_SCRATCH_BYTES / 24 points FP64, / 16
+        mixed; concurrent calls on one GPU race)."""
+        self._call(self.lib.sp6_step_noalloc, _ptr(F, "F", self.shape), ctypes.c_double(dt), ctypes.c_int32(nsteps))
+        return F
+
     def step_radial_implicit(self, F, dt, nsteps=1):
         """Split steps in place on F: RK4 on the angular and collision terms, then
         a backward-Euler radial step (no radial step limit)."""
