@@ -30,4 +30,4 @@ listed in each function's docstring.
 """
 
 from .grid import Grid, make_grid  # noqa: F401
-from . import ops, step, adjoint, diagnostics, closed_forms  # noqa: F401
+from . import ops, step, adjoint, diagnostics, closed_forms, conservative  # noqa: F401

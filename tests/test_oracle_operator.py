@@ -412,3 +412,55 @@ def test_config1_closed_form_report():
     l2 = np.linalg.norm((y - want).ravel()) / np.linalg.norm(want.ravel())
     print(f"config 1 oracle vs closed form after {cfg.steps} steps: max-rel {mr:.3e} L2-rel {l2:.3e}")
     assert l2 < 0.15 and mr < 0.3
+
+
+def test_flux_forms_are_the_same_operator():
+    # Eq. (Cohercons) is the transport equation times V: on data the grid
+    # represents exactly (x-degree 2, angular degree 2), the flux form of every
+    # term and the hybrid form equal Eq. (Liouvsph)
+    from oracle import conservative as cons
+    F = synth.fields.polynomial_state(synth.config(1).scaled(n_r=9), seed=3, deg_x=2, deg_om=2)
+    g = og.make_grid(*F.shape)
+    L = ops.apply_L(F, g)
+    assert nrm(cons.apply_L_hybrid(F, g), L) <= 1e-12
+    assert nrm(cons.apply_L_flux(F, g), L) <= 1e-12
+
+
+def test_flux_form_radial_phi_Phi_balance_exactly():
+    # the parts of the flux form that cancel for any nodal data: the sum of
+    # D_r(cos Theta F^) with Clenshaw-Curtis weights is the boundary difference of
+    # cos Theta F^ (the quadrature is exact on the derivative of the interpolant);
+    # Fourier derivatives along phi and Phi sum to zero over a period
+    g = og.make_grid(1, 9, 4, 8, 4, 8)
+    X = np.random.default_rng(23).normal(size=g.shape)
+    cT = np.cos(g.mesh()[3])
+    rsum = np.tensordot(g.w_r, ops.d_r(cT * X, g), axes=([0], [1]))
+    np.testing.assert_allclose(rsum, (cT * X)[:, -1] - (cT * X)[:, 0], atol=1e-12)
+    assert np.max(np.abs(ops.d_phi(X, g).sum(axis=3))) <= 1e-12
+    assert np.max(np.abs(ops.d_Phi(X, g).sum(axis=5))) <= 1e-12
+
+
+def test_conservation_residual_of_the_three_forms():
+    # Eq. (Cons) at one instant on the workload-1 beam (no inflow mask): the
+    # residual dN/dt + J_R2 - J_R1 relative to |J_R2| + |J_R1| for Eq. (Liouvsph)
+    # as built, the full flux form of Eq. (Cohercons) and the hybrid (radial and
+    # Phi terms in flux form).  Measured on this grid (17 x 8 x 16 x 8 x 16):
+    # 5.40e-3, 3.78e-2 and 5.40e-3.  The hybrid equals the form as built to
+    # rounding: Clenshaw-Curtis integrates the radial terms of both exactly (the
+    # interpolant's r^2 p' + 2 r p has degree n_r, one more than the rule's
+    # guaranteed n_r - 1, but the symmetric rule is exact there too) and the
+    # trapezoid rule the Phi terms, so the whole residual comes from the theta and
+    # Theta DFS lines.  The full flux form is worse there: the theta line of
+    # F^ = V F is odd across the pole.  Neither form is built on the GPU.
+    from oracle import conservative as cons
+    cfg = synth.config(1)
+    g = og.make_grid(*cfg.shape)
+    F = synth.fields.beam(cfg)
+    res = {}
+    for name, fn in (("liouvsph", ops.apply_L), ("flux", cons.apply_L_flux), ("hybrid", cons.apply_L_hybrid)):
+        r, s = cons.conservation_residual(fn(F, g), F, g)
+        res[name] = float(abs(r[0]) / s[0])
+    print("Eq. (Cons) relative residual on the beam: " + ", ".join(f"{k} {v:.2e}" for k, v in res.items()))
+    assert 4e-3 < res["liouvsph"] < 7e-3
+    assert abs(res["hybrid"] - res["liouvsph"]) <= 1e-10
+    assert res["flux"] > 5 * res["liouvsph"]
