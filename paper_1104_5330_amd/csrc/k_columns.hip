@@ -572,6 +572,176 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
   }
 }
 
+// ---------------------------------------------------------------------------
+// theta and phi terms together on the 32 x 64 position sphere (FP64).  A tile of
+// CW = 8 in-plane columns, closed under the DFS partner map (two runs of four
+// columns of one Theta row, the second at Phi + pi), holds all 32 x 64 = 2048
+// values of each column in LDS (132 KB: one workgroup per CU).  Both line
+// directions run as FP64 MFMA products (v_mfma_f64_16x16x4f64) on the even/odd
+// halves of the 64-point operator:
+//   theta: P = A E, Q = B O with E, O = Y(theta_j, phi_k, c) +- Y(theta_j,
+//          phi_k + pi, c') (the DFS line of column c at phi_k and, reversed, its
+//          partner), one GEMM column per line (k, c);
+//   phi  : the same with E, O = Y(theta_l, phi_j, c) +- Y(theta_l, phi_63-j, c),
+//          one GEMM column per line (theta_l, c).
+// Outputs i and 63 - i of a line are P + Q and Q - P.  The A and B blocks of the
+// operator (32 x 32 each) stay in registers: a wavefront takes one 16-row block
+// and four 16-line blocks.  The theta results go through LDS to the phi results'
+// owners, and T is stored from LDS with the staging pattern: the state is read
+// once and T written once (16 bytes per point instead of 40 for the two
+// separate passes).
+
+template <int CW>
+struct S64 {
+  static constexpr int NTH = 32, NPH = 64, L = 64;
+  static constexpr int R = CW / 2;                     // run length (columns)
+  static constexpr int NW = 2 * CW;                    // wavefronts: CW theta, CW phi
+  static constexpr int NTHR = 64 * NW;
+  // theta-row stride in LDS (doubles): the row groups of one LDS access fall on
+  // different banks
+  static constexpr int RS = NPH * CW + 16;
+  static constexpr int NE = NTH * NPH * CW;            // values per tile
+  static constexpr int LDSN = NTH * RS;
+  static constexpr int PPT = NE / (2 * NTHR);          // column pairs per thread
+  static SP6_DEV int at(int th, int ph, int col) { return th * RS + ph * CW + col; }
+  static_assert(NE % (2 * NTHR) == 0, "pairs divide evenly");
+};
+
+template <int CW>
+__global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, const double* __restrict__ Y,
+                                                          double* __restrict__ T, double coef_sign, int mask_in,
+                                                          double in_scale, int ntiles) {
+  using C = S64<CW>;
+  constexpr int NTH = C::NTH, NPH = C::NPH, R = C::R;
+  __shared__ __align__(16) double sY[C::LDSN];
+  // blocks b, b + 8, ... (one XCD) take the G tiles whose runs share 128-byte lines
+  constexpr int G = 128 / (R * 8);
+  const int b = d.rev ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
+  const int tile = (b / (8 * G)) * (8 * G) + (b % 8) * G + (b / 8) % G;
+  if (tile >= ntiles) return;
+  const int tpp = d.plane / CW;
+  const int ej = tile / tpp, tl = tile - ej * tpp;
+  const int j = ej % d.n_r;
+  const int hP = d.n_Ph >> 1;
+  const int tpr = hP / R;
+  const int cbase = (tl / tpr) * d.n_Ph + (tl % tpr) * R;
+  auto colc = [&](int col) { return cbase + (col & (R - 1)) + ((col & R) ? hP : 0); };
+  const int64_t slab = int64_t(ej) * d.M;
+  const int plane = d.plane;
+  const int tid = int(threadIdx.x);
+  const int lane = tid & 63;
+  const int wave = wave_uniform(tid >> 6);
+
+  // stage the tile with 16-byte loads of two neighbouring columns of a run
+  {
+    const int q = tid % (CW / 2);
+    const int c = colc(2 * q);
+    double s_in = in_scale;
+    if (mask_in && is_inflow(d, t, j, c / d.n_Ph)) s_in = 0.0;
+    double2 v[C::PPT];
+#pragma unroll
+    for (int i = 0; i < C::PPT; ++i) {
+      const int p = tid + i * C::NTHR;  // pair p = combo * CW / 2 + q, combo = theta * 64 + phi
+      v[i] = *reinterpret_cast<const double2*>(Y + (slab + int64_t(p / (CW / 2)) * plane + c));
+    }
+#pragma unroll
+    for (int i = 0; i < C::PPT; ++i) {
+      const int p = tid + i * C::NTHR;
+      const int combo = p / (CW / 2);
+      *reinterpret_cast<double2*>(&sY[C::at(combo / NPH, combo % NPH, 2 * q)]) =
+          double2{v[i].x * s_in, v[i].y * s_in};
+    }
+  }
+  // this wavefront's 16-row block of the even (A) and odd (B) operator halves:
+  // MFMA A operand, lane l holds row ib * 16 + l % 16, column 4 s + l / 16
+  const bool isTh = wave < CW;
+  const int wd = isTh ? wave : wave - CW;
+  const int ib = wd & 1, ng = wd >> 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const double* tab = line_tab<64>(LT_DERIV);
+  double aA[8], aB[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    aA[s] = tab[(ib * 16 + lr) * 32 + 4 * s + lk];
+    aB[s] = tab[32 * 32 + (ib * 16 + lr) * 32 + 4 * s + lk];
+  }
+  __syncthreads();
+
+  // four 16-line blocks per wavefront; line n of the theta GEMM is (k, col) =
+  // (n / CW, n % CW), of the phi GEMM (theta_l, col) = (n / CW, n % CW)
+  v4d accP[4], accQ[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) accP[u] = accQ[u] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const int jj = 4 * s + lk;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int n = (ng * 4 + u) * 16 + lr;
+      const int a = n / CW, col = n % CW;
+      double x, y;
+      if (isTh) {
+        x = sY[C::at(jj, a, col)];
+        y = sY[C::at(jj, a + NTH, col ^ R)];
+      } else {
+        x = sY[C::at(a, jj, col)];
+        y = sY[C::at(a, NPH - 1 - jj, col)];
+      }
+      accP[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aA[s], x + y, accP[u], 0, 0, 0);
+      accQ[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aB[s], x - y, accQ[u], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // every read of the staged tile is done
+  // C layout: register v holds row lk + 4 v, line lr of the 16 x 16 block
+  if (isTh) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int n = (ng * 4 + u) * 16 + lr;
+      const int k = n / CW, col = n % CW;
+      const int c = colc(col);
+      const double sc = coef_sign * t.sin_Th[c / d.n_Ph] * t.cos_Ph[c % d.n_Ph] * t.inv_r[j];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ib * 16 + lk + 4 * v;
+        // element i: (theta_i, phi_k, c); element 63 - i: (theta_i, phi_k + pi, c').  The
+        // partner's coefficient is -sc and its derivative the negated DFS value:
+        // both take sc times the line output.
+        sY[C::at(i, k, col)] = sc * (accP[u][v] + accQ[u][v]);
+        sY[C::at(i, k + NTH, col ^ R)] = sc * (accQ[u][v] - accP[u][v]);
+      }
+    }
+  }
+  __syncthreads();
+  if (!isTh) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int n = (ng * 4 + u) * 16 + lr;
+      const int l = n / CW, col = n % CW;
+      const int c = colc(col);
+      const double sc =
+          coef_sign * t.sin_Th[c / d.n_Ph] * t.sin_Ph[c % d.n_Ph] * t.inv_r[j] * t.inv_sin_th[l];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = ib * 16 + lk + 4 * v;
+        sY[C::at(l, i, col)] += sc * (accP[u][v] + accQ[u][v]);
+        sY[C::at(l, NPH - 1 - i, col)] += sc * (accQ[u][v] - accP[u][v]);
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int q = tid % (CW / 2);
+    const int c = colc(2 * q);
+#pragma unroll
+    for (int i = 0; i < C::PPT; ++i) {
+      const int p = tid + i * C::NTHR;
+      const int combo = p / (CW / 2);
+      *reinterpret_cast<double2*>(T + (slab + int64_t(combo) * plane + c)) =
+          *reinterpret_cast<const double2*>(&sY[C::at(combo / NPH, combo % NPH, 2 * q)]);
+    }
+  }
+}
+
 unsigned grid_for(int64_t threads) { return unsigned((threads + CB - 1) / CB); }
 
 template <int L, typename TI, typename TO>
@@ -645,6 +815,23 @@ int sphere_cw(const KDims& d) {
   return d.plane < 16 ? d.plane : 16;
 }
 
+// the 32 x 64 sphere (FP64 path): tiles of 8 columns, which need n_Phi >= 16 (a
+// tile is two runs within one Theta row).  The mixed path keeps the separate
+// theta and phi passes there: an FP32 form of the fused pass (66 KB tiles) ran at
+// 6.6 ms per launch on the 4-group large grid against 4.6 ms for the two passes.
+bool sphere64_ok(const KDims& d) { return d.n_th == 32 && d.n_ph == 64 && d.n_Ph >= 16; }
+
+hipError_t launch_sphere64(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign, bool mask_in,
+                           double in_scale, hipStream_t s) {
+  constexpr int CW = 8;
+  const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
+  constexpr int64_t GB = 8 * (128 / (CW / 2 * 8));
+  const int64_t nb = (ntiles + GB - 1) / GB * GB;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  k_sphere64<CW><<<unsigned(nb), S64<CW>::NTHR, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale, int(ntiles));
+  return hipGetLastError();
+}
+
 template <int NTH, int CW, typename TI, typename TC>
 hipError_t launch_sphere_t(const KDims& d, const KTab& t, const void* Y, void* T, double coef_sign, bool mask_in,
                            double in_scale, hipStream_t s) {
@@ -693,10 +880,11 @@ hipError_t launch_theta_mixed(const KDims& d, const KTab& t, const void* Y, bool
                : launch_theta_p<double, float>(d, t, Y, T, accum, 1.0, false, 1.0, s);
 }
 
-bool sphere_fusable(const KDims& d, bool) { return sphere_cw(d) > 0; }
+bool sphere_fusable(const KDims& d, bool mixed) { return sphere_cw(d) > 0 || (!mixed && sphere64_ok(d)); }
 
 hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
                          bool mask_in, double in_scale, hipStream_t s) {
+  if (sphere64_ok(d)) return launch_sphere64(d, t, Y, T, coef_sign, mask_in, in_scale, s);
   switch (sphere_cw(d)) {
     case 8: return launch_sphere_n<8, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
     case 16: return launch_sphere_n<16, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);

@@ -59,6 +59,16 @@ struct PC {
     const int pl = p / PLANE, r = p % PLANE;
     return pl * PS + (r / NF) * RS + (r % NF);
   }
+  // plane row (Theta index) of the point tid + q NTHR a thread stages: when the
+  // workgroup covers whole rows and a plane is a whole number of workgroup rounds,
+  // tid / NF plus a constant per q (one base address with immediate offsets for
+  // the row tables instead of one address per point)
+  static SP6_DEV int row_of(int tid, int q) {
+    if constexpr (NTHR % NF == 0 && PLANE % NTHR == 0)
+      return tid / NF + (q * (NTHR / NF)) % NT;
+    else
+      return ((tid + q * NTHR) % PLANE) / NF;
+  }
 };
 
 struct PlaneIdx {
@@ -226,6 +236,13 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   __shared__ TC sR[2][C::PTSP];
   __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT], sWm[NT];
   __shared__ PlaneInfo sPl[C::NPW];
+  // isotropic in-scattering on 16 x 32 and 32 x 64 planes: the angular mean is
+  // summed from the values each thread stages (row weight times value), reduced
+  // over the wavefront and then over the wavefronts in a fixed order, instead of
+  // by one wavefront over the staged rows (which held a per-lane address for every
+  // row element and spilled registers on the 2048-point planes)
+  constexpr bool MEAN_STAGED = NT >= 16 && !AN;
+  __shared__ double sMean[MEAN_STAGED ? C::NW : 1][C::NPW];
   __shared__ double sMo[AN ? C::NPW : 1][NMOM];
   __shared__ double sInvR[SP6_MAX_NR], sCot[32];
 
@@ -239,8 +256,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   // instead of eight times (FP64 RK4 step 2 % faster, mixed 1 %).
   constexpr bool MFL = NT == 16 && C::NW == 4 && C::NPW == 2 &&
                        ((sizeof(TY) == 8 && sizeof(TC) == 8) || sizeof(TC) == 4);
-  __shared__ TC sTab[MFL ? 2 * NT * NT : 1];
-  if constexpr (MFL) {
+  // 32 x 64 planes (one plane per workgroup, eight wavefronts): the same products
+  // with wavefront w taking direction w mod 2, output block (w / 2) mod 2 and line
+  // block w / 4 of the 32 x 32 even and odd halves
+  constexpr bool MFL32 = NT == 32 && C::NW == 8 && C::NPW == 1;
+  __shared__ TC sTab[(MFL || MFL32) ? 2 * NT * NT : 1];
+  if constexpr (MFL || MFL32) {
     const TC* tab = line_tab<C::L, TC>(LT_DERIV_T);
     for (int i = tid; i < 2 * NT * NT; i += C::NTHR) sTab[i] = tab[i];
   }
@@ -319,6 +340,15 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   // the last stage (acc read, no y) loads acc for the current group after the
   // group barrier instead of one group ahead: fewer registers
   constexpr bool NA_AHEAD = NA && (NY || YA);
+  // inflow nodes (Sect. 4.2) among this thread's points: cos Theta > 0 (inflow at
+  // r_in) and < 0 (inflow at r_out), one bit per point
+  uint32_t cpos = 0, cneg = 0;
+#pragma unroll
+  for (int q = 0; q < C::PPT; ++q) {
+    const double cT = sCT[C::row_of(tid, q)];
+    cpos |= uint32_t(cT > 0.0) << q;
+    cneg |= uint32_t(cT < 0.0) << q;
+  }
   TY yin[C::PPT];
   TO tn[C::PPT];
   double an[NA_AHEAD ? C::PPT : 1], yn[NY ? C::PPT : 1];
@@ -333,6 +363,21 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
     const int plane0 = grp * C::NPW;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) sY[C::lds(tid + q * C::NTHR)] = yin[q];
+    if constexpr (MEAN_STAGED) {
+      if (scat) {
+        static_assert(C::PLANE % C::NTHR == 0, "a thread's staged point q lies in plane q NTHR / PLANE");
+        double mp[C::NPW];
+#pragma unroll
+        for (int pl = 0; pl < C::NPW; ++pl) mp[pl] = 0.0;
+#pragma unroll
+        for (int q = 0; q < C::PPT; ++q) mp[(q * C::NTHR) / C::PLANE] += sWm[C::row_of(tid, q)] * double(yin[q]);
+#pragma unroll
+        for (int pl = 0; pl < C::NPW; ++pl) {
+          const double v = plane_rows_sum<64>(mp[pl]);
+          if ((tid & 63) == 0) sMean[tid >> 6][pl] = v;
+        }
+      }
+    }
     if (tid < C::NPW) {
       const int pid = min(plane0 + tid, npl - 1);
       const int l = (pid >> sh_ph) & (d.n_th - 1);
@@ -425,6 +470,13 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
             }
           }
         }
+      } else if (MEAN_STAGED) {
+        if (scat && tid < C::NPW) {
+          double m = 0.0;
+#pragma unroll
+          for (int w = 0; w < C::NW; ++w) m += sMean[w][tid];
+          sPl[tid].mean = m;
+        }
       } else if (scat && part == 0) {
         // weighted row sum of each Phi row (FP64), reduced over the NT Phi lanes of the plane
         double s = 0.0;
@@ -436,7 +488,56 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         s = plane_rows_sum<NT>(s);
         if (li == NT) sPl[pl].mean = s;
       }
-      if constexpr (MFL) {
+      if constexpr (MFL32) {
+        // Theta (w even): P = A E, Q = B O over the 32 DFS lines (column c and,
+        // reversed, c + 32), input index j = s + 8 (l / 16) so that the two row
+        // groups a 16-lane LDS access spans fall on different banks; Phi (w odd):
+        // P = E A^T, Q = O B^T over the 32 rows, j = 4 s + l / 16.  Outputs q and
+        // 63 - q of a line are P + Q and Q - P.
+        const bool th = (part & 1) == 0;
+        const int ib = (part >> 1) & 1, nb = part >> 2;
+        const int lr = lane & 15, lk = lane >> 4;
+        using VC = typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type;
+        auto mfma = [](TC a, TC b, VC c) {
+          if constexpr (sizeof(TC) == 8)
+            return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+          else
+            return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        };
+        VC cp = {0, 0, 0, 0}, cq = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NT / 4; ++s) {
+          const int jj = th ? s + 8 * lk : 4 * s + lk;
+          const TC ta = sTab[jj * NT + ib * 16 + lr], tb = sTab[NT * NT + jj * NT + ib * 16 + lr];
+          if (th) {
+            const TC x = TC(sY[jj * C::RS + nb * 16 + lr]), y = TC(sY[jj * C::RS + nb * 16 + lr + NT]);
+            cp = mfma(ta, x + y, cp);
+            cq = mfma(tb, x - y, cq);
+          } else {
+            const int row = nb * 16 + lr;
+            const TC x = TC(sY[row * C::RS + jj]), y = TC(sY[row * C::RS + (C::L - 1 - jj)]);
+            cp = mfma(x + y, ta, cp);
+            cq = mfma(x - y, tb, cq);
+          }
+        }
+        const double ir = sPl[0].inv_r, ct = sPl[0].cot_th;
+        // C row of register v: interleaved for the FP64 product, in blocks of four
+        // for the FP32 one
+        const int r0 = sizeof(TC) == 8 ? lk : 4 * lk, rs = sizeof(TC) == 8 ? 4 : 1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const TC pv = cp[v] + cq[v], qv = cq[v] - cp[v];
+          if (th) {  // output a of column nb 16 + lr, and a of its partner column
+            const int a = ib * 16 + r0 + rs * v, col = nb * 16 + lr;
+            sR[0][a * C::RS + col] = TC(line_coef<NT>(true, a, col, ir, ct, sTh, sPh) * pv);
+            sR[0][a * C::RS + col + NT] = TC(line_coef<NT>(true, C::L - 1 - a, col, ir, ct, sTh, sPh) * qv);
+          } else {  // row nb 16 + r0 + rs v: outputs ib 16 + lr and 63 - that
+            const int row = nb * 16 + r0 + rs * v, q = ib * 16 + lr;
+            sR[1][row * C::RS + q] = TC(line_coef<NT>(false, q, NT + row, ir, ct, sTh, sPh) * pv);
+            sR[1][row * C::RS + (C::L - 1 - q)] = TC(line_coef<NT>(false, C::L - 1 - q, NT + row, ir, ct, sTh, sPh) * qv);
+          }
+        }
+      } else if constexpr (MFL) {
         // Theta (w even): P = A^T E, Q = B^T O with E, O = Y[j][c] +- Y[j][c + 16]
         // (the DFS line of column c and its reversed partner half); Phi (w odd):
         // P = E A, Q = O B with E, O = Y[i][j] +- Y[i][31 - j].  Outputs q and
@@ -509,16 +610,15 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         st_stream<NT_PLANE_ST>(a.out + gp, LY);
         continue;
       }
-      const int iTh = (p % C::PLANE) / C::NF;
       const PlaneInfo& pi = sPl[pl];
       const double Yv = double(sY[lp]);
       double inscat = pi.mean;
       if constexpr (AN) {
-        const int m = p % C::NF;
+        const int iTh = C::row_of(tid, q), m = p % C::NF;
         inscat = phase_contract(cf, sMo[pl], sCT[iTh], sTh[iTh] * sCP[m], sTh[iTh] * sPh[m]);
       }
       double k = -LY + pi.eta - (pi.kappa + pi.sigma) * Yv + pi.sigma * inscat;
-      if (d.bc && ((pi.j == 0 && sCT[iTh] > 0.0) || (pi.j == d.n_r - 1 && sCT[iTh] < 0.0))) k = 0.0;
+      if (d.bc && ((pi.j == 0 && ((cpos >> q) & 1u)) || (pi.j == d.n_r - 1 && ((cneg >> q) & 1u)))) k = 0.0;
       if (a.mode == PM_RHS) {
         st_stream<NT_PLANE_ST>(a.out + gp, k);
         continue;

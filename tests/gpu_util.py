@@ -47,3 +47,16 @@ def small(cfg_id, **kw):
 
 def banner(msg):
     print(f"[gpu-test] {msg}", flush=True)
+
+
+def stable_dt(cfg):
+    """The workload rule dt = 0.2 (r_1 - r_0), capped so that the stiffest angular
+    term stays inside RK4's stability interval on the imaginary axis (about 2.8):
+    the phi and Phi derivatives carry 1/sin(theta), and at the first half-shifted
+    node theta_0 = pi / (2 n_theta) with r = r_in their rate is (n / 2) / (r_in
+    sin theta_0).  Every workload's own dt is below the cap; small test grids that
+    pair a short radial line with fine angles are not."""
+    import math
+    s0 = math.sin(math.pi / (2 * cfg.n_theta))
+    lam = max(cfg.n_phi, cfg.n_Phi) / 2 / (cfg.r_in * s0)
+    return min(cfg.dt, 0.5 / lam)

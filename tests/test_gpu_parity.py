@@ -8,7 +8,7 @@ import torch
 
 import synth
 from oracle import ops, step, adjoint, diagnostics
-from tests.gpu_util import need_gpu, maxrel, l2rel, to_dev, to_host, oracle_grid, small, banner
+from tests.gpu_util import need_gpu, maxrel, l2rel, to_dev, to_host, oracle_grid, small, banner, stable_dt
 
 pytestmark = pytest.mark.gpu
 
@@ -18,8 +18,10 @@ TOL = 1e-12
 # the small workload, a reduced workload-2 shape, one of each line length, a
 # wide (Theta, Phi) plane whose fused theta-phi tiles are split Theta rows, the
 # radial lengths of the large workloads (n_r = 33: nine 4-row k-steps; n_r = 65:
-# seventeen, five 16-row tiles, the last one ragged), and one (eps, r) slab
-# set of the large grid's angular shape (theta lines of 64 points, 2048-point planes)
+# seventeen, five 16-row tiles, the last one ragged), one (eps, r) slab set of the
+# large grid's angular shape (theta lines of 64 points, 2048-point planes), and
+# the 32 x 64 position sphere on small planes (fused theta-phi tiles spanning two
+# Theta rows of a 128-byte line; odd n_eps * n_r, so the last workgroups are idle)
 SHAPES = {
     "tiny": small(3, n_eps=1, n_r=5, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
     "ragged": small(3, n_eps=3, n_r=7, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
@@ -31,6 +33,8 @@ SHAPES = {
     "r33": small(3, n_eps=3, n_r=33, n_theta=2, n_phi=4, n_Theta=4, n_Phi=8),
     "r65": small(3, n_eps=1, n_r=65, n_theta=4, n_phi=8, n_Theta=4, n_Phi=8),
     "w5_slab": small(5, n_eps=1, n_r=3),
+    "s64_small": small(5, n_eps=1, n_r=3, n_Theta=8, n_Phi=16),
+    "s64_ragged": small(5, n_eps=3, n_r=5, n_Theta=8, n_Phi=16),
 }
 SHAPES["cfg1"] = synth.config(1).scaled(physics="scatter")
 
@@ -92,13 +96,13 @@ def test_rhs_switches(bc, scat):
 
 
 @pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "big_lines", "wide_plane", "r33", "r65",
-                                  "w5_slab"])
+                                  "w5_slab", "s64_small", "s64_ragged"])
 def test_step(name):
     cfg = SHAPES[name]
     banner(f"step {name}")
     G, F, (k, s, e) = setup(cfg, seed=5)
     g = oracle_grid(cfg)
-    dt = cfg.dt
+    dt = stable_dt(cfg)
     p = step.Physics(k, s, e, bc=True, scattering=True)
     want = step.run(F, g, p, dt, 3)
     Fd = to_dev(F)
@@ -116,13 +120,14 @@ def test_step_is_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "wide_plane", "r33", "r65"])
+@pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "wide_plane", "r33", "r65", "s64_small",
+                                  "s64_ragged"])
 def test_adjoint_step(name):
     cfg = SHAPES[name]
     banner(f"adjoint {name}")
     G, F, (k, s, e) = setup(cfg, seed=7)
     g = oracle_grid(cfg)
-    dt = cfg.dt
+    dt = stable_dt(cfg)
     p = step.Physics(k, s, e, bc=True, scattering=True)
     lam = synth.fields.random_state(cfg, 8)
     lam_prev, gk, ge, gs = adjoint.adjoint_step(F, lam, g, p, dt)
