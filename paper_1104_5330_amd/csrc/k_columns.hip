@@ -576,20 +576,21 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 // theta and phi terms together on the 32 x 64 position sphere (FP64).  A tile of
 // CW = 8 in-plane columns, closed under the DFS partner map (two runs of four
 // columns of one Theta row, the second at Phi + pi), holds all 32 x 64 = 2048
-// values of each column in LDS (132 KB: one workgroup per CU).  Both line
-// directions run as FP64 MFMA products (v_mfma_f64_16x16x4f64) on the even/odd
-// halves of the 64-point operator:
+// values of each column in LDS (132 KB; 148 KB with the operator: one workgroup
+// per CU).  Both line directions run as FP64 MFMA products
+// (v_mfma_f64_16x16x4f64) on the even/odd halves of the 64-point operator:
 //   theta: P = A E, Q = B O with E, O = Y(theta_j, phi_k, c) +- Y(theta_j,
 //          phi_k + pi, c') (the DFS line of column c at phi_k and, reversed, its
 //          partner), one GEMM column per line (k, c);
 //   phi  : the same with E, O = Y(theta_l, phi_j, c) +- Y(theta_l, phi_63-j, c),
 //          one GEMM column per line (theta_l, c).
 // Outputs i and 63 - i of a line are P + Q and Q - P.  The A and B blocks of the
-// operator (32 x 32 each) stay in registers: a wavefront takes one 16-row block
-// and four 16-line blocks.  The theta results go through LDS to the phi results'
-// owners, and T is stored from LDS with the staging pattern: the state is read
-// once and T written once (16 bytes per point instead of 40 for the two
-// separate passes).
+// operator (32 x 32 each, 16 KB) sit in LDS in the MFMA operand order: a
+// wavefront takes one 16-row block and four 16-line blocks, and reads its
+// operand column and the points of four lines at each k-step.  The theta
+// results go through LDS to the phi results' owners, and T is stored from LDS
+// with the staging pattern: the state is read once and T written once (16 bytes
+// per point instead of 40 for the two separate passes).
 
 template <int CW>
 struct S64 {
@@ -614,6 +615,9 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
   using C = S64<CW>;
   constexpr int NTH = C::NTH, NPH = C::NPH, R = C::R;
   __shared__ __align__(16) double sY[C::LDSN];
+  // operator halves in the MFMA A-operand lane order: [A, B][row block][s][lane]
+  __shared__ __align__(16) double sTab[2 * 2 * 8 * 64];
+  __shared__ double sIs[NTH];  // 1 / sin(theta_l)
   // blocks b, b + 8, ... (one XCD) take the G tiles whose runs share 128-byte lines
   constexpr int G = 128 / (R * 8);
   const int b = d.rev ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
@@ -652,45 +656,68 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
           double2{v[i].x * s_in, v[i].y * s_in};
     }
   }
-  // this wavefront's 16-row block of the even (A) and odd (B) operator halves:
-  // MFMA A operand, lane l holds row ib * 16 + l % 16, column 4 s + l / 16
+  {
+    const double* tab = line_tab<64>(LT_DERIV);
+#pragma unroll
+    for (int r = 0; r < 2 * 2 * 8 * 64 / C::NTHR; ++r) {
+      const int e = tid + r * C::NTHR;
+      const int ab = e >> 10, rb = (e >> 9) & 1, s = (e >> 6) & 7, l = e & 63;
+      sTab[e] = tab[ab * 32 * 32 + (rb * 16 + (l & 15)) * 32 + 4 * s + (l >> 4)];
+    }
+    if (tid < NTH) sIs[tid] = t.inv_sin_th[tid];
+  }
   const bool isTh = wave < CW;
   const int wd = isTh ? wave : wave - CW;
   const int ib = wd & 1, ng = wd >> 1;
   const int lr = lane & 15, lk = lane >> 4;
-  const double* tab = line_tab<64>(LT_DERIV);
-  double aA[8], aB[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    aA[s] = tab[(ib * 16 + lr) * 32 + 4 * s + lk];
-    aB[s] = tab[32 * 32 + (ib * 16 + lr) * 32 + 4 * s + lk];
+  // the column coefficient of this lane's lines (column lr % CW in every block),
+  // loaded before the products so that its latency is hidden
+  double sc0;
+  {
+    const int c = colc(lr % CW);
+    sc0 = coef_sign * t.sin_Th[c / d.n_Ph] * (isTh ? t.cos_Ph[c % d.n_Ph] : t.sin_Ph[c % d.n_Ph]) * t.inv_r[j];
   }
   __syncthreads();
 
   // four 16-line blocks per wavefront; line n of the theta GEMM is (k, col) =
-  // (n / CW, n % CW), of the phi GEMM (theta_l, col) = (n / CW, n % CW)
+  // (n / CW, n % CW), of the phi GEMM (theta_l, col) = (n / CW, n % CW).  One
+  // straight product loop per direction (uniform over the wavefront).
   v4d accP[4], accQ[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) accP[u] = accQ[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  auto products = [&](auto dir) {
+    constexpr bool TH = decltype(dir)::value;
 #pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const int jj = 4 * s + lk;
+    for (int s = 0; s < 8; ++s) {
+      const int jj = 4 * s + lk;
+      const double a0 = sTab[(ib * 8 + s) * 64 + lane];
+      const double b0 = sTab[((2 + ib) * 8 + s) * 64 + lane];
+      double x[4], y[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int n = (ng * 4 + u) * 16 + lr;
-      const int a = n / CW, col = n % CW;
-      double x, y;
-      if (isTh) {
-        x = sY[C::at(jj, a, col)];
-        y = sY[C::at(jj, a + NTH, col ^ R)];
-      } else {
-        x = sY[C::at(a, jj, col)];
-        y = sY[C::at(a, NPH - 1 - jj, col)];
+      for (int u = 0; u < 4; ++u) {
+        const int n = (ng * 4 + u) * 16 + lr;
+        const int a = n / CW, col = n % CW;
+        if constexpr (TH) {
+          x[u] = sY[C::at(jj, a, col)];
+          y[u] = sY[C::at(jj, a + NTH, col ^ R)];
+        } else {
+          x[u] = sY[C::at(a, jj, col)];
+          y[u] = sY[C::at(a, NPH - 1 - jj, col)];
+        }
       }
-      accP[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aA[s], x + y, accP[u], 0, 0, 0);
-      accQ[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(aB[s], x - y, accQ[u], 0, 0, 0);
+      // all ten LDS reads of the step are in flight before the first product
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        accP[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x[u] + y[u], accP[u], 0, 0, 0);
+        accQ[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, x[u] - y[u], accQ[u], 0, 0, 0);
+      }
     }
-  }
+  };
+  if (isTh)
+    products(std::true_type{});
+  else
+    products(std::false_type{});
   __syncthreads();  // every read of the staged tile is done
   // C layout: register v holds row lk + 4 v, line lr of the 16 x 16 block
   if (isTh) {
@@ -698,16 +725,14 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
     for (int u = 0; u < 4; ++u) {
       const int n = (ng * 4 + u) * 16 + lr;
       const int k = n / CW, col = n % CW;
-      const int c = colc(col);
-      const double sc = coef_sign * t.sin_Th[c / d.n_Ph] * t.cos_Ph[c % d.n_Ph] * t.inv_r[j];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = ib * 16 + lk + 4 * v;
         // element i: (theta_i, phi_k, c); element 63 - i: (theta_i, phi_k + pi, c').  The
-        // partner's coefficient is -sc and its derivative the negated DFS value:
-        // both take sc times the line output.
-        sY[C::at(i, k, col)] = sc * (accP[u][v] + accQ[u][v]);
-        sY[C::at(i, k + NTH, col ^ R)] = sc * (accQ[u][v] - accP[u][v]);
+        // partner's coefficient is -sc0 and its derivative the negated DFS value:
+        // both take sc0 times the line output.
+        sY[C::at(i, k, col)] = sc0 * (accP[u][v] + accQ[u][v]);
+        sY[C::at(i, k + NTH, col ^ R)] = sc0 * (accQ[u][v] - accP[u][v]);
       }
     }
   }
@@ -717,9 +742,7 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
     for (int u = 0; u < 4; ++u) {
       const int n = (ng * 4 + u) * 16 + lr;
       const int l = n / CW, col = n % CW;
-      const int c = colc(col);
-      const double sc =
-          coef_sign * t.sin_Th[c / d.n_Ph] * t.sin_Ph[c % d.n_Ph] * t.inv_r[j] * t.inv_sin_th[l];
+      const double sc = sc0 * sIs[l];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = ib * 16 + lk + 4 * v;
@@ -730,11 +753,15 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
   }
   __syncthreads();
   {
-    const int q = tid % (CW / 2);
+    // the thread index through an opaque copy: the store addresses are formed
+    // here, not kept in registers from the staging loads
+    int td = tid;
+    asm volatile("" : "+v"(td));
+    const int q = td % (CW / 2);
     const int c = colc(2 * q);
 #pragma unroll
     for (int i = 0; i < C::PPT; ++i) {
-      const int p = tid + i * C::NTHR;
+      const int p = td + i * C::NTHR;
       const int combo = p / (CW / 2);
       *reinterpret_cast<double2*>(T + (slab + int64_t(combo) * plane + c)) =
           *reinterpret_cast<const double2*>(&sY[C::at(combo / NPH, combo % NPH, 2 * q)]);
