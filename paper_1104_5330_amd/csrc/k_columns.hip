@@ -588,8 +588,8 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 // operator (32 x 32 each, 16 KB) sit in LDS in the MFMA operand order: a
 // wavefront takes one 16-row block and four 16-line blocks, and reads its
 // operand column and the points of four lines at each k-step.  The theta
-// results go through LDS to the phi results' owners, and T is stored from LDS
-// with the staging pattern: the state is read once and T written once (16 bytes
+// results go through LDS to the phi results' owners, which add their own and
+// store T from registers: the state is read once and T written once (16 bytes
 // per point instead of 40 for the two separate passes).
 
 template <int CW>
@@ -738,33 +738,20 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
   }
   __syncthreads();
   if (!isTh) {
+    // the phi wavefronts add their results to the theta results in LDS and store
+    // T from registers: rows l of two runs of four columns per 16-lane group
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int n = (ng * 4 + u) * 16 + lr;
       const int l = n / CW, col = n % CW;
       const double sc = sc0 * sIs[l];
+      const int64_t ob = slab + int64_t(l) * NPH * plane + colc(col);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = ib * 16 + lk + 4 * v;
-        sY[C::at(l, i, col)] += sc * (accP[u][v] + accQ[u][v]);
-        sY[C::at(l, NPH - 1 - i, col)] += sc * (accQ[u][v] - accP[u][v]);
+        T[ob + int64_t(i) * plane] = sY[C::at(l, i, col)] + sc * (accP[u][v] + accQ[u][v]);
+        T[ob + int64_t(NPH - 1 - i) * plane] = sY[C::at(l, NPH - 1 - i, col)] + sc * (accQ[u][v] - accP[u][v]);
       }
-    }
-  }
-  __syncthreads();
-  {
-    // the thread index through an opaque copy: the store addresses are formed
-    // here, not kept in registers from the staging loads
-    int td = tid;
-    asm volatile("" : "+v"(td));
-    const int q = td % (CW / 2);
-    const int c = colc(2 * q);
-#pragma unroll
-    for (int i = 0; i < C::PPT; ++i) {
-      const int p = td + i * C::NTHR;
-      const int combo = p / (CW / 2);
-      *reinterpret_cast<double2*>(T + (slab + int64_t(combo) * plane + c)) =
-          *reinterpret_cast<const double2*>(&sY[C::at(combo / NPH, combo % NPH, 2 * q)]);
     }
   }
 }
