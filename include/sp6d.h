@@ -180,9 +180,9 @@ sp6_status sp6_step_ab2(sp6_grid grid, double* F, double* H, double dt, int32_t 
  * synchronised) kernel_ms[c] holds the summed duration and launches[c] the number
  * of launches of kernel class c: 0 phi pass, 1 theta pass, 2 radial pass, 3 plane
  * pass (Theta, Phi, collision, inflow, RK stage), 4 filter, 5 theta and phi
- * passes fused into one (used when n_phi = 2 n_theta <= 32, and on FP64 handles
- * for n_theta = 32, n_phi = 64, n_Phi >= 16).  Both arrays are
- * host arrays of 6 entries.  For measurement only. */
+ * passes fused into one (used when n_phi = 2 n_theta <= 32, and for n_theta = 32,
+ * n_phi = 64, n_Phi >= 16).  Both arrays are host arrays of 6 entries.  For
+ * measurement only. */
 sp6_status sp6_step_timed(sp6_grid grid, double* F, double dt, int32_t nsteps, double* kernel_ms,
                           int64_t* launches);
 

@@ -144,6 +144,8 @@ __global__ __launch_bounds__(CB) void k_theta(KDims d, KTab t, const TI* __restr
 //   C (16 x 16): register v holds C[l / 16 + 4 v][l % 16] (rows interleaved).
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 
 template <int KS, bool ACCUM>
 __global__ __launch_bounds__(CB) void k_radial(KDims d, KTab t, const double* __restrict__ Y,
@@ -592,13 +594,16 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 // store T from registers: the state is read once and T written once (16 bytes
 // per point instead of 40 for the two separate passes).
 
-template <int CW>
+template <int CW, int NW_, typename TC>
 struct S64 {
   static constexpr int NTH = 32, NPH = 64, L = 64;
   static constexpr int R = CW / 2;                     // run length (columns)
-  static constexpr int NW = 2 * CW;                    // wavefronts: CW theta, CW phi
+  static constexpr int NW = NW_;                       // wavefronts: NW / 2 theta, NW / 2 phi
   static constexpr int NTHR = 64 * NW;
-  // theta-row stride in LDS (doubles): the row groups of one LDS access fall on
+  // 16-line blocks per wavefront: each direction has 2 CW blocks of 16 lines
+  // times two 16-row blocks of the operator halves, over NW / 2 wavefronts
+  static constexpr int U = 8 * CW / NW;
+  // theta-row stride in LDS (elements): the row groups of one LDS access fall on
   // different banks
   static constexpr int RS = NPH * CW + 16;
   static constexpr int NE = NTH * NPH * CW;            // values per tile
@@ -606,20 +611,39 @@ struct S64 {
   static constexpr int PPT = NE / (2 * NTHR);          // column pairs per thread
   static SP6_DEV int at(int th, int ph, int col) { return th * RS + ph * CW + col; }
   static_assert(NE % (2 * NTHR) == 0, "pairs divide evenly");
+  static_assert(U * NW == 8 * CW, "line blocks divide evenly");
 };
 
-template <int CW>
-__global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, const double* __restrict__ Y,
-                                                          double* __restrict__ T, double coef_sign, int mask_in,
-                                                          double in_scale, int ntiles) {
-  using C = S64<CW>;
-  constexpr int NTH = C::NTH, NPH = C::NPH, R = C::R;
-  __shared__ __align__(16) double sY[C::LDSN];
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  using type = double2;
+};
+template <>
+struct Pair2<float> {
+  using type = float2;
+};
+
+// TI: stored type of the state read; TC: LDS, product and T type (FP64 path:
+// double, double on v_mfma_f64_16x16x4f64; mixed path: double or float in, float
+// on v_mfma_f32_16x16x4f32).
+template <int CW, int NW, typename TI, typename TC>
+__global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI* __restrict__ Y,
+                                                      TC* __restrict__ T, double coef_sign, int mask_in,
+                                                      double in_scale, int ntiles) {
+  using C = S64<CW, NW, TC>;
+  using TI2 = typename Pair2<TI>::type;
+  using TC2 = typename Pair2<TC>::type;
+  using VC = typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type;
+  constexpr bool F64 = sizeof(TC) == 8;
+  constexpr int NTH = C::NTH, NPH = C::NPH, R = C::R, U = C::U;
+  __shared__ __align__(16) TC sY[C::LDSN];
   // operator halves in the MFMA A-operand lane order: [A, B][row block][s][lane]
-  __shared__ __align__(16) double sTab[2 * 2 * 8 * 64];
+  __shared__ __align__(16) TC sTab[2 * 2 * 8 * 64];
   __shared__ double sIs[NTH];  // 1 / sin(theta_l)
   // blocks b, b + 8, ... (one XCD) take the G tiles whose runs share 128-byte lines
-  constexpr int G = 128 / (R * 8);
+  constexpr int G = 128 / (R * int(sizeof(TI)));
   const int b = d.rev ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
   const int tile = (b / (8 * G)) * (8 * G) + (b % 8) * G + (b / 8) % G;
   if (tile >= ntiles) return;
@@ -636,38 +660,47 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
   const int lane = tid & 63;
   const int wave = wave_uniform(tid >> 6);
 
-  // stage the tile with 16-byte loads of two neighbouring columns of a run
+  // stage the tile with loads of two neighbouring columns of a run per lane
   {
     const int q = tid % (CW / 2);
     const int c = colc(2 * q);
     double s_in = in_scale;
     if (mask_in && is_inflow(d, t, j, c / d.n_Ph)) s_in = 0.0;
-    double2 v[C::PPT];
+    TI2 v[C::PPT];
 #pragma unroll
     for (int i = 0; i < C::PPT; ++i) {
       const int p = tid + i * C::NTHR;  // pair p = combo * CW / 2 + q, combo = theta * 64 + phi
-      v[i] = *reinterpret_cast<const double2*>(Y + (slab + int64_t(p / (CW / 2)) * plane + c));
+      v[i] = *reinterpret_cast<const TI2*>(Y + (slab + int64_t(p / (CW / 2)) * plane + c));
     }
 #pragma unroll
     for (int i = 0; i < C::PPT; ++i) {
       const int p = tid + i * C::NTHR;
       const int combo = p / (CW / 2);
-      *reinterpret_cast<double2*>(&sY[C::at(combo / NPH, combo % NPH, 2 * q)]) =
-          double2{v[i].x * s_in, v[i].y * s_in};
+      TC2 w;
+      if constexpr (F64) {
+        w.x = v[i].x * s_in;
+        w.y = v[i].y * s_in;
+      } else {
+        w.x = TC(v[i].x);
+        w.y = TC(v[i].y);
+      }
+      *reinterpret_cast<TC2*>(&sY[C::at(combo / NPH, combo % NPH, 2 * q)]) = w;
     }
   }
   {
-    const double* tab = line_tab<64>(LT_DERIV);
+    const TC* tab = line_tab<64, TC>(LT_DERIV);
 #pragma unroll
-    for (int r = 0; r < 2 * 2 * 8 * 64 / C::NTHR; ++r) {
+    for (int r = 0; r < (2 * 2 * 8 * 64 + C::NTHR - 1) / C::NTHR; ++r) {
       const int e = tid + r * C::NTHR;
-      const int ab = e >> 10, rb = (e >> 9) & 1, s = (e >> 6) & 7, l = e & 63;
-      sTab[e] = tab[ab * 32 * 32 + (rb * 16 + (l & 15)) * 32 + 4 * s + (l >> 4)];
+      if (e < 2 * 2 * 8 * 64) {
+        const int ab = e >> 10, rb = (e >> 9) & 1, s = (e >> 6) & 7, l = e & 63;
+        sTab[e] = tab[ab * 32 * 32 + (rb * 16 + (l & 15)) * 32 + 4 * s + (l >> 4)];
+      }
     }
     if (tid < NTH) sIs[tid] = t.inv_sin_th[tid];
   }
-  const bool isTh = wave < CW;
-  const int wd = isTh ? wave : wave - CW;
+  const bool isTh = wave < NW / 2;
+  const int wd = isTh ? wave : wave - NW / 2;
   const int ib = wd & 1, ng = wd >> 1;
   const int lr = lane & 15, lk = lane >> 4;
   // the column coefficient of this lane's lines (column lr % CW in every block),
@@ -676,26 +709,33 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
   {
     const int c = colc(lr % CW);
     sc0 = coef_sign * t.sin_Th[c / d.n_Ph] * (isTh ? t.cos_Ph[c % d.n_Ph] : t.sin_Ph[c % d.n_Ph]) * t.inv_r[j];
+    if constexpr (!F64) sc0 *= in_scale;  // FP32 tiles are staged unscaled
   }
   __syncthreads();
 
-  // four 16-line blocks per wavefront; line n of the theta GEMM is (k, col) =
+  // U 16-line blocks per wavefront; line n of the theta GEMM is (k, col) =
   // (n / CW, n % CW), of the phi GEMM (theta_l, col) = (n / CW, n % CW).  One
   // straight product loop per direction (uniform over the wavefront).
-  v4d accP[4], accQ[4];
+  VC accP[U], accQ[U];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) accP[u] = accQ[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < U; ++u) accP[u] = accQ[u] = VC{0, 0, 0, 0};
+  auto mfma = [](TC a, TC x, VC c) {
+    if constexpr (F64)
+      return __builtin_amdgcn_mfma_f64_16x16x4f64(a, x, c, 0, 0, 0);
+    else
+      return __builtin_amdgcn_mfma_f32_16x16x4f32(a, x, c, 0, 0, 0);
+  };
   auto products = [&](auto dir) {
     constexpr bool TH = decltype(dir)::value;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int jj = 4 * s + lk;
-      const double a0 = sTab[(ib * 8 + s) * 64 + lane];
-      const double b0 = sTab[((2 + ib) * 8 + s) * 64 + lane];
-      double x[4], y[4];
+      const TC a0 = sTab[(ib * 8 + s) * 64 + lane];
+      const TC b0 = sTab[((2 + ib) * 8 + s) * 64 + lane];
+      TC x[U], y[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int n = (ng * 4 + u) * 16 + lr;
+      for (int u = 0; u < U; ++u) {
+        const int n = (ng * U + u) * 16 + lr;
         const int a = n / CW, col = n % CW;
         if constexpr (TH) {
           x[u] = sY[C::at(jj, a, col)];
@@ -705,12 +745,12 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
           y[u] = sY[C::at(a, NPH - 1 - jj, col)];
         }
       }
-      // all ten LDS reads of the step are in flight before the first product
+      // all LDS reads of the step are in flight before the first product
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        accP[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x[u] + y[u], accP[u], 0, 0, 0);
-        accQ[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0, x[u] - y[u], accQ[u], 0, 0, 0);
+      for (int u = 0; u < U; ++u) {
+        accP[u] = mfma(a0, x[u] + y[u], accP[u]);
+        accQ[u] = mfma(b0, x[u] - y[u], accQ[u]);
       }
     }
   };
@@ -719,36 +759,38 @@ __global__ __launch_bounds__(S64<CW>::NTHR) void k_sphere64(KDims d, KTab t, con
   else
     products(std::false_type{});
   __syncthreads();  // every read of the staged tile is done
-  // C layout: register v holds row lk + 4 v, line lr of the 16 x 16 block
+  // C layout: register v holds row lk + 4 v (FP64 product) or 4 lk + v (FP32)
+  auto crow = [&](int v) { return ib * 16 + (F64 ? lk + 4 * v : 4 * lk + v); };
   if (isTh) {
+    const TC sc = TC(sc0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int n = (ng * 4 + u) * 16 + lr;
+    for (int u = 0; u < U; ++u) {
+      const int n = (ng * U + u) * 16 + lr;
       const int k = n / CW, col = n % CW;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = ib * 16 + lk + 4 * v;
-        // element i: (theta_i, phi_k, c); element 63 - i: (theta_i, phi_k + pi, c').  The
-        // partner's coefficient is -sc0 and its derivative the negated DFS value:
-        // both take sc0 times the line output.
-        sY[C::at(i, k, col)] = sc0 * (accP[u][v] + accQ[u][v]);
-        sY[C::at(i, k + NTH, col ^ R)] = sc0 * (accQ[u][v] - accP[u][v]);
+        const int i = crow(v);
+        // element i: (theta_i, phi_k, c); element 63 - i: (theta_i, phi_k + pi, c').
+        // The partner's coefficient is -sc and its derivative the negated DFS
+        // value: both take sc times the line output.
+        sY[C::at(i, k, col)] = sc * (accP[u][v] + accQ[u][v]);
+        sY[C::at(i, k + NTH, col ^ R)] = sc * (accQ[u][v] - accP[u][v]);
       }
     }
   }
   __syncthreads();
   if (!isTh) {
     // the phi wavefronts add their results to the theta results in LDS and store
-    // T from registers: rows l of two runs of four columns per 16-lane group
+    // T from registers: rows l of two runs of columns per 16-lane group
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int n = (ng * 4 + u) * 16 + lr;
+    for (int u = 0; u < U; ++u) {
+      const int n = (ng * U + u) * 16 + lr;
       const int l = n / CW, col = n % CW;
-      const double sc = sc0 * sIs[l];
+      const TC sc = TC(sc0 * sIs[l]);
       const int64_t ob = slab + int64_t(l) * NPH * plane + colc(col);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = ib * 16 + lk + 4 * v;
+        const int i = crow(v);
         T[ob + int64_t(i) * plane] = sY[C::at(l, i, col)] + sc * (accP[u][v] + accQ[u][v]);
         T[ob + int64_t(NPH - 1 - i) * plane] = sY[C::at(l, NPH - 1 - i, col)] + sc * (accQ[u][v] - accP[u][v]);
       }
@@ -829,21 +871,32 @@ int sphere_cw(const KDims& d) {
   return d.plane < 16 ? d.plane : 16;
 }
 
-// the 32 x 64 sphere (FP64 path): tiles of 8 columns, which need n_Phi >= 16 (a
-// tile is two runs within one Theta row).  The mixed path keeps the separate
-// theta and phi passes there: an FP32 form of the fused pass (66 KB tiles) ran at
-// 6.6 ms per launch on the 4-group large grid against 4.6 ms for the two passes.
+// the 32 x 64 sphere: tiles of 8 (FP64) or 16 (FP32) columns, two runs within one
+// Theta row (n_Phi >= 16)
 bool sphere64_ok(const KDims& d) { return d.n_th == 32 && d.n_ph == 64 && d.n_Ph >= 16; }
+
+template <int CW, int NW, typename TI, typename TC>
+hipError_t launch_sphere64_t(const KDims& d, const KTab& t, const TI* Y, TC* T, double coef_sign, bool mask_in,
+                             double in_scale, hipStream_t s) {
+  const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
+  constexpr int64_t GB = 8 * (128 / (CW / 2 * int64_t(sizeof(TI))));
+  const int64_t nb = (ntiles + GB - 1) / GB * GB;
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  k_sphere64<CW, NW, TI, TC><<<unsigned(nb), 64 * NW, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale, int(ntiles));
+  return hipGetLastError();
+}
 
 hipError_t launch_sphere64(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign, bool mask_in,
                            double in_scale, hipStream_t s) {
-  constexpr int CW = 8;
-  const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
-  constexpr int64_t GB = 8 * (128 / (CW / 2 * 8));
-  const int64_t nb = (ntiles + GB - 1) / GB * GB;
-  if (nb > INT32_MAX) return hipErrorInvalidValue;
-  k_sphere64<CW><<<unsigned(nb), S64<CW>::NTHR, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale, int(ntiles));
-  return hipGetLastError();
+  return launch_sphere64_t<8, 16>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
+}
+
+// FP32 tiles of 16 columns (32-byte runs of an FP32 row, 133 KB of LDS): 3.89 ms
+// per launch on the 4-group large grid, against 3.95 for 8-column tiles (16-byte
+// runs, two workgroups per CU) and 4.44 for the separate theta and phi passes
+hipError_t launch_sphere64_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, hipStream_t s) {
+  return y_f32 ? launch_sphere64_t<16, 16>(d, t, static_cast<const float*>(Y), T, 1.0, false, 1.0, s)
+               : launch_sphere64_t<16, 16>(d, t, static_cast<const double*>(Y), T, 1.0, false, 1.0, s);
 }
 
 template <int NTH, int CW, typename TI, typename TC>
@@ -894,7 +947,7 @@ hipError_t launch_theta_mixed(const KDims& d, const KTab& t, const void* Y, bool
                : launch_theta_p<double, float>(d, t, Y, T, accum, 1.0, false, 1.0, s);
 }
 
-bool sphere_fusable(const KDims& d, bool mixed) { return sphere_cw(d) > 0 || (!mixed && sphere64_ok(d)); }
+bool sphere_fusable(const KDims& d, bool mixed) { return sphere_cw(d) > 0 || sphere64_ok(d); }
 
 hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
                          bool mask_in, double in_scale, hipStream_t s) {
@@ -908,6 +961,7 @@ hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double*
 
 hipError_t launch_sphere_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T,
                                hipStream_t s) {
+  if (sphere64_ok(d)) return launch_sphere64_mixed(d, t, Y, y_f32, T, s);
   switch (sphere_cw(d)) {
     case 8:
       return y_f32 ? launch_sphere_n<8, float, float>(d, t, Y, T, 1.0, false, 1.0, s)

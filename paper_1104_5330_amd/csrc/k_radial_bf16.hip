@@ -61,7 +61,14 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
   auto atT = [&](float* row) { return reinterpret_cast<float*>(reinterpret_cast<char*>(row) + offC); };
   // every extent is a power of two: divisions become shifts
   const int sh_g = __builtin_ctz(gpe), sh_P = __builtin_ctz(d.n_Ph);
-  for (int k = int(blockIdx.x) * NWV + wave; k < ngroups; k += gstride) {
+  // a wavefront takes the two column groups of a 128-byte FP32 row segment one
+  // after the other, so that the second half of each line is read while the
+  // first half's fetch is still in L2
+  for (int k2 = int(blockIdx.x) * NWV + wave; 2 * k2 < ngroups; k2 += gstride)
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    const int k = 2 * k2 + h;
+    if (k >= ngroups) break;
     const int g = d.rev ? ngroups - 1 - k : k;
     const int e = g >> sh_g;
     const int c0 = (g & (gpe - 1)) * 16;

@@ -121,8 +121,8 @@ hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T,
 hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
                         double coef_sign, bool mask_in, double in_scale, hipStream_t s);
 // theta and phi terms together into T (not accumulated), for n_phi = 2 n_theta,
-// n_theta <= 16, and on the FP64 path also for the 32 x 64 sphere with n_Phi >= 16;
-// the separate passes take every other shape
+// n_theta <= 16, and for the 32 x 64 sphere with n_Phi >= 16; the separate passes
+// take every other shape
 bool sphere_fusable(const KDims& d, bool mixed);
 hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
                          bool mask_in, double in_scale, hipStream_t s);
