@@ -588,8 +588,9 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 //          one GEMM column per line (theta_l, c).
 // Outputs i and 63 - i of a line are P + Q and Q - P.  The A and B blocks of the
 // operator (32 x 32 each, 16 KB) sit in LDS in the MFMA operand order: a
-// wavefront takes one 16-row block and four 16-line blocks, and reads its
-// operand column and the points of four lines at each k-step.  The theta
+// wavefront takes both 16-row blocks for U / 2 16-line blocks, and reads the
+// operand columns and its lines' points at each k-step (each point serving four
+// products).  The theta
 // results go through LDS to the phi results' owners, which add their own and
 // store T from registers: the state is read once and T written once (16 bytes
 // per point instead of 40 for the two separate passes).
@@ -700,11 +701,11 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
     if (tid < NTH) sIs[tid] = t.inv_sin_th[tid];
   }
   const bool isTh = wave < NW / 2;
-  const int wd = isTh ? wave : wave - NW / 2;
-  const int ib = wd & 1, ng = wd >> 1;
+  // a wavefront takes both 16-row blocks of the operator halves for U / 2 line
+  // blocks: each staged point it reads serves four products
+  const int ng = isTh ? wave : wave - NW / 2;
+  constexpr int UH = U / 2;
   const int lr = lane & 15, lk = lane >> 4;
-  // the column coefficient of this lane's lines (column lr % CW in every block),
-  // loaded before the products so that its latency is hidden
   double sc0;
   {
     const int c = colc(lr % CW);
@@ -713,12 +714,11 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
   }
   __syncthreads();
 
-  // U 16-line blocks per wavefront; line n of the theta GEMM is (k, col) =
-  // (n / CW, n % CW), of the phi GEMM (theta_l, col) = (n / CW, n % CW).  One
-  // straight product loop per direction (uniform over the wavefront).
-  VC accP[U], accQ[U];
+  VC accP[2][UH], accQ[2][UH];
 #pragma unroll
-  for (int u = 0; u < U; ++u) accP[u] = accQ[u] = VC{0, 0, 0, 0};
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int u = 0; u < UH; ++u) accP[h][u] = accQ[h][u] = VC{0, 0, 0, 0};
   auto mfma = [](TC a, TC x, VC c) {
     if constexpr (F64)
       return __builtin_amdgcn_mfma_f64_16x16x4f64(a, x, c, 0, 0, 0);
@@ -730,12 +730,15 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
       const int jj = 4 * s + lk;
-      const TC a0 = sTab[(ib * 8 + s) * 64 + lane];
-      const TC b0 = sTab[((2 + ib) * 8 + s) * 64 + lane];
-      TC x[U], y[U];
+      TC a0[2], b0[2], x[UH], y[UH];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int n = (ng * U + u) * 16 + lr;
+      for (int h = 0; h < 2; ++h) {
+        a0[h] = sTab[(h * 8 + s) * 64 + lane];
+        b0[h] = sTab[((2 + h) * 8 + s) * 64 + lane];
+      }
+#pragma unroll
+      for (int u = 0; u < UH; ++u) {
+        const int n = (ng * UH + u) * 16 + lr;
         const int a = n / CW, col = n % CW;
         if constexpr (TH) {
           x[u] = sY[C::at(jj, a, col)];
@@ -745,12 +748,15 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
           y[u] = sY[C::at(a, NPH - 1 - jj, col)];
         }
       }
-      // all LDS reads of the step are in flight before the first product
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        accP[u] = mfma(a0, x[u] + y[u], accP[u]);
-        accQ[u] = mfma(b0, x[u] - y[u], accQ[u]);
+      for (int u = 0; u < UH; ++u) {
+        const TC e = x[u] + y[u], o = x[u] - y[u];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          accP[h][u] = mfma(a0[h], e, accP[h][u]);
+          accQ[h][u] = mfma(b0[h], o, accQ[h][u]);
+        }
       }
     }
   };
@@ -760,41 +766,40 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
     products(std::false_type{});
   __syncthreads();  // every read of the staged tile is done
   // C layout: register v holds row lk + 4 v (FP64 product) or 4 lk + v (FP32)
-  auto crow = [&](int v) { return ib * 16 + (F64 ? lk + 4 * v : 4 * lk + v); };
+  auto crow = [&](int h, int v) { return h * 16 + (F64 ? lk + 4 * v : 4 * lk + v); };
   if (isTh) {
     const TC sc = TC(sc0);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int n = (ng * U + u) * 16 + lr;
-      const int k = n / CW, col = n % CW;
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = crow(v);
-        // element i: (theta_i, phi_k, c); element 63 - i: (theta_i, phi_k + pi, c').
-        // The partner's coefficient is -sc and its derivative the negated DFS
-        // value: both take sc times the line output.
-        sY[C::at(i, k, col)] = sc * (accP[u][v] + accQ[u][v]);
-        sY[C::at(i, k + NTH, col ^ R)] = sc * (accQ[u][v] - accP[u][v]);
+      for (int u = 0; u < UH; ++u) {
+        const int n = (ng * UH + u) * 16 + lr;
+        const int k = n / CW, col = n % CW;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = crow(h, v);
+          sY[C::at(i, k, col)] = sc * (accP[h][u][v] + accQ[h][u][v]);
+          sY[C::at(i, k + NTH, col ^ R)] = sc * (accQ[h][u][v] - accP[h][u][v]);
+        }
       }
-    }
   }
   __syncthreads();
   if (!isTh) {
-    // the phi wavefronts add their results to the theta results in LDS and store
-    // T from registers: rows l of two runs of columns per 16-lane group
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int n = (ng * U + u) * 16 + lr;
-      const int l = n / CW, col = n % CW;
-      const TC sc = TC(sc0 * sIs[l]);
-      const int64_t ob = slab + int64_t(l) * NPH * plane + colc(col);
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = crow(v);
-        T[ob + int64_t(i) * plane] = sY[C::at(l, i, col)] + sc * (accP[u][v] + accQ[u][v]);
-        T[ob + int64_t(NPH - 1 - i) * plane] = sY[C::at(l, NPH - 1 - i, col)] + sc * (accQ[u][v] - accP[u][v]);
+      for (int u = 0; u < UH; ++u) {
+        const int n = (ng * UH + u) * 16 + lr;
+        const int l = n / CW, col = n % CW;
+        const TC sc = TC(sc0 * sIs[l]);
+        const int64_t ob = slab + int64_t(l) * NPH * plane + colc(col);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = crow(h, v);
+          T[ob + int64_t(i) * plane] = sY[C::at(l, i, col)] + sc * (accP[h][u][v] + accQ[h][u][v]);
+          T[ob + int64_t(NPH - 1 - i) * plane] = sY[C::at(l, NPH - 1 - i, col)] + sc * (accQ[h][u][v] - accP[h][u][v]);
+        }
       }
-    }
   }
 }
 
