@@ -63,31 +63,34 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
   const int sh_g = __builtin_ctz(gpe), sh_P = __builtin_ctz(d.n_Ph);
   // a wavefront takes the two column groups of a 128-byte FP32 row segment one
   // after the other, so that the second half of each line is read while the
-  // first half's fetch is still in L2
-  for (int k2 = int(blockIdx.x) * NWV + wave; 2 * k2 < ngroups; k2 += gstride)
-#pragma unroll 1
-  for (int h = 0; h < 2; ++h) {
-    const int k = 2 * k2 + h;
-    if (k >= ngroups) break;
+  // first half's fetch is still in L2; with few row tiles (registers to spare)
+  // both groups' loads are issued before either group's products
+  constexpr int TVN = ACCUM ? NRT * 4 : 1;
+  constexpr bool PAIRLOAD = NRT <= 3;
+  struct Group {
+    float y[KS][8];
+    float tv[TVN];
+    float cT;
+    int64_t gb;
+  };
+  auto load = [&](int k, Group& G) {
     const int g = d.rev ? ngroups - 1 - k : k;
     const int e = g >> sh_g;
     const int c0 = (g & (gpe - 1)) * 16;
-    const float cT = float(t.cos_Th[((c0 + lr) >> sh_P) & (d.n_Th - 1)]);
-    const int64_t gb = int64_t(e) * n_r * M + c0;
-    const TI* __restrict__ Yg = Y + gb;
-    float* __restrict__ Tg = T + gb;
-    float y[KS][8];
+    G.cT = float(t.cos_Th[((c0 + lr) >> sh_P) & (d.n_Th - 1)]);
+    G.gb = int64_t(e) * n_r * M + c0;
+    const TI* __restrict__ Yg = Y + G.gb;
+    float* __restrict__ Tg = T + G.gb;
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const TI* row = Yg + int64_t(32 * s + q) * M;
         if (s < KS - 1)
-          y[s][q] = float(ldY(row));
+          G.y[s][q] = float(ldY(row));
         else
-          y[s][q] = 32 * s + 8 * lg + q < n_r ? float(ldY(row)) : 0.0f;
+          G.y[s][q] = 32 * s + 8 * lg + q < n_r ? float(ldY(row)) : 0.0f;
       }
-    float tv[ACCUM ? NRT * 4 : 1];
     if constexpr (ACCUM) {
 #pragma unroll
       for (int rt = 0; rt < NRT; ++rt)
@@ -95,18 +98,21 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
         for (int v = 0; v < 4; ++v) {
           float* row = Tg + int64_t(16 * rt + v) * M;
           if (rt < NRT - 1)
-            tv[rt * 4 + v] = *atT(row);
+            G.tv[rt * 4 + v] = *atT(row);
           else
-            tv[rt * 4 + v] = 16 * rt + 4 * lg + v < n_r ? *atT(row) : 0.0f;
+            G.tv[rt * 4 + v] = 16 * rt + 4 * lg + v < n_r ? *atT(row) : 0.0f;
         }
     }
+  };
+  auto compute = [&](const Group& G) {
+    float* __restrict__ Tg = T + G.gb;
     v8bf B[3][KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         __bf16 b1, b2, b3;
-        split3(y[s][q], b1, b2, b3);
+        split3(G.y[s][q], b1, b2, b3);
         B[0][s][q] = b1;
         B[1][s][q] = b2;
         B[2][s][q] = b3;
@@ -131,14 +137,32 @@ __global__ __launch_bounds__(CB) void k_radial_bf16x3(KDims d, KTab t, const TI*
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         if (rt < NRT - 1 || 16 * rt + 4 * lg + v < n_r) {
-          const float val = cT * acc[rt][v];
+          const float val = G.cT * acc[rt][v];
           float* dst = atT(Tg + int64_t(16 * rt + v) * M);
           if constexpr (ACCUM)
-            *dst = tv[rt * 4 + v] + val;
+            *dst = G.tv[rt * 4 + v] + val;
           else
             *dst = val;
         }
       }
+  };
+  for (int k2 = int(blockIdx.x) * NWV + wave; 2 * k2 < ngroups; k2 += gstride) {
+    const bool two = 2 * k2 + 1 < ngroups;
+    if constexpr (PAIRLOAD) {
+      Group G0, G1;
+      load(2 * k2, G0);
+      if (two) load(2 * k2 + 1, G1);
+      compute(G0);
+      if (two) compute(G1);
+    } else {
+      Group G0;
+      load(2 * k2, G0);
+      compute(G0);
+      if (two) {
+        load(2 * k2 + 1, G0);
+        compute(G0);
+      }
+    }
   }
 }
 
