@@ -575,25 +575,26 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 }
 
 // ---------------------------------------------------------------------------
-// theta and phi terms together on the 32 x 64 position sphere (FP64).  A tile of
-// CW = 8 in-plane columns, closed under the DFS partner map (two runs of four
-// columns of one Theta row, the second at Phi + pi), holds all 32 x 64 = 2048
-// values of each column in LDS (132 KB; 148 KB with the operator: one workgroup
-// per CU).  Both line directions run as FP64 MFMA products
-// (v_mfma_f64_16x16x4f64) on the even/odd halves of the 64-point operator:
+// theta and phi terms together on the 32 x 64 position sphere.  A tile of CW
+// in-plane columns, closed under the DFS partner map (two runs of CW / 2 columns
+// of one Theta row, the second at Phi + pi), holds all 32 x 64 = 2048 values of
+// each column in LDS: FP64 tiles of 8 columns (132 KB, 148 KB with the
+// operator: one workgroup per CU), FP32 tiles of 16 (the mixed path, 32-byte
+// runs).  Both line directions run as MFMA products (v_mfma_f64_16x16x4f64, or
+// v_mfma_f32_16x16x4f32) on the even/odd halves of the 64-point operator:
 //   theta: P = A E, Q = B O with E, O = Y(theta_j, phi_k, c) +- Y(theta_j,
 //          phi_k + pi, c') (the DFS line of column c at phi_k and, reversed, its
 //          partner), one GEMM column per line (k, c);
 //   phi  : the same with E, O = Y(theta_l, phi_j, c) +- Y(theta_l, phi_63-j, c),
 //          one GEMM column per line (theta_l, c).
 // Outputs i and 63 - i of a line are P + Q and Q - P.  The A and B blocks of the
-// operator (32 x 32 each, 16 KB) sit in LDS in the MFMA operand order: a
-// wavefront takes both 16-row blocks for U / 2 16-line blocks, and reads the
-// operand columns and its lines' points at each k-step (each point serving four
-// products).  The theta
-// results go through LDS to the phi results' owners, which add their own and
-// store T from registers: the state is read once and T written once (16 bytes
-// per point instead of 40 for the two separate passes).
+// operator (32 x 32 each) sit in LDS in the MFMA operand order: a wavefront
+// takes both 16-row blocks for U / 2 16-line blocks, and reads the operand
+// columns and its lines' points at each k-step (each point serving four
+// products).  The theta results go through LDS to the phi results' owners, which
+// add their own and store T from registers: the state is read once and T
+// written once (16 bytes per point in FP64 instead of 40 for the two separate
+// passes).
 
 template <int CW, int NW_, typename TC>
 struct S64 {
