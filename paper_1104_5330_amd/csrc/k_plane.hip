@@ -643,23 +643,37 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
 //   (K = avg for isotropic scattering: sum u (K Y_s) = <Y_s> sum u)
 // Transposed line: v_q = coef_q u_q; z = D v; result_q = -z_q (D^T = -D).
 
-// four waves per SIMD (128 VGPRs; the 16 x 32 and 32 x 64 planes spill a few
-// registers): measured 10 % faster per adjoint step than three
+// four waves per SIMD (128 VGPRs): measured 10 % faster per adjoint step than
+// three
 template <int NT, bool AN>
 __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4))) void k_plane_adj(KDims d, KTab t, KCoef cf, AdjArgs a,
                                                             double* lt_out) {
   using C = PC<NT>;
+  // isotropic scattering on 16 x 32 and 32 x 64 planes: the plane sums of u,
+  // u Y_s and w Y_s (for K^T u and the gradients) are summed from the values each
+  // thread loads, reduced over the wavefront and then over the wavefronts in a
+  // fixed order, instead of by one wavefront over the staged rows ahead of its
+  // lines (Y_s is then not staged)
+  constexpr bool RED_STAGED = NT >= 16 && !AN;
+  static_assert(!RED_STAGED || C::PLANE % C::NTHR == 0, "a thread's point q lies in plane q NTHR / PLANE");
   __shared__ double sU[C::PTSP];
-  __shared__ double sY[C::PTSP];
+  __shared__ double sY[RED_STAGED ? 1 : C::PTSP];
   __shared__ double sR[2][C::PTSP];
-  __shared__ double sRed[C::NPW * NT][3];
+  __shared__ double sRed[RED_STAGED ? 1 : C::NPW * NT][3];
+  __shared__ double sRedW[RED_STAGED ? C::NW : 1][C::NPW][3];
   __shared__ double sMoU[AN ? C::NPW : 1][NMOM], sMoY[AN ? C::NPW : 1][NMOM];
-  __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT];
+  __shared__ double sTh[NT], sPh[C::NF], sCP[C::NF], sCT[NT], sWm[NT];
+  // per plane of the workgroup: geometric factors, coefficients, radial index
+  struct AdjPlane {
+    double inv_r, cot_th, kappa, sigma;
+    int j, pad;
+  };
+  __shared__ AdjPlane sPA[C::NPW];
 
   const int tid = threadIdx.x;
-  const int64_t plane0 = int64_t(blockIdx.x) * C::NPW;
-  const int64_t gbase = plane0 * C::PLANE;
-  const int64_t npl = d.nplanes;
+  const int npl = int(d.nplanes);
+  const int plane0 = int(blockIdx.x) * C::NPW;
+  const int64_t gbase = int64_t(plane0) * C::PLANE;
   const bool lt = lt_out != nullptr;
   // 16 x 32 planes: the transposed lines as the MFMA products of the forward
   // pass, on the coefficient-weighted input (adjoint step 5.82 -> 5.42 ms on the
@@ -674,31 +688,76 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4)
   if (tid < NT) {
     sTh[tid] = t.sin_Th[tid];
     sCT[tid] = t.cos_Th[tid];
+    sWm[tid] = t.wmean[tid];
   }
   if (tid < C::NF) {
     sPh[tid] = t.sin_Ph[tid];
     sCP[tid] = t.cos_Ph[tid];
   }
+  if (tid < C::NPW) {
+    // plane index (e, j, l, k) with k fastest; n_phi and n_theta are powers of two
+    const int pid = min(plane0 + tid, npl - 1);
+    const int sh_ph = __builtin_ctz(d.n_ph), sh_th = __builtin_ctz(d.n_th);
+    const int l = (pid >> sh_ph) & (d.n_th - 1);
+    const int j = (pid >> (sh_ph + sh_th)) % d.n_r;
+    AdjPlane pa;
+    pa.inv_r = t.inv_r[j];
+    pa.cot_th = t.cot_th[l];
+    pa.kappa = lt ? 0.0 : cf.kappa[pid];
+    pa.sigma = (!lt && d.scattering) ? cf.sigma[pid] : 0.0;
+    pa.j = j;
+    pa.pad = 0;
+    sPA[tid] = pa;
+  }
+  __syncthreads();
 
   double xr[C::PPT], tv[C::PPT], lv[C::PPT], cv[C::PPT];
+  double ru[RED_STAGED ? C::NPW : 1], ruy[RED_STAGED ? C::NPW : 1], rwy[RED_STAGED ? C::NPW : 1];
+#pragma unroll
+  for (int pl = 0; pl < (RED_STAGED ? C::NPW : 1); ++pl) ru[pl] = ruy[pl] = rwy[pl] = 0.0;
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int p = tid + q * C::NTHR;
-    const int64_t pid = plane0 + p / C::PLANE;
-    const bool ok = pid < npl;
+    const int pl = p / C::PLANE;
+    const bool ok = plane0 + pl < npl;
     const int64_t gp = gbase + p;
+    const int iTh = (p % C::PLANE) / C::NF;
     const double x = ok ? ld_stream<NT_ADJ_LD>(a.x + gp) : 0.0;
     xr[q] = x;
     double u = lt ? x : a.xs * x;
-    if (!lt && ok) {
-      const PlaneIdx pi = plane_index(d, pid);
-      if (is_inflow(d, t, pi.j, (p % C::PLANE) / C::NF)) u = 0.0;
+    if (!lt && d.bc) {  // inflow nodes (Sect. 4.2) are held: u = 0 there
+      const int j = sPA[pl].j;
+      const double c = sCT[iTh];
+      if ((j == 0 && c > 0.0) || (j == d.n_r - 1 && c < 0.0)) u = 0.0;
     }
     sU[C::lds(p)] = u;
-    if (grads) sY[C::lds(p)] = ok ? ld_stream<NT_ADJ_LD>(a.Ys + gp) : 0.0;
+    const double ys = (grads && ok) ? ld_stream<NT_ADJ_LD>(a.Ys + gp) : 0.0;
+    if constexpr (RED_STAGED) {
+      const int rp = (q * C::NTHR) / C::PLANE;
+      ru[rp] += u;
+      ruy[rp] += u * ys;
+      rwy[rp] += sWm[iTh] * ys;
+    } else {
+      if (grads) sY[C::lds(p)] = ys;
+    }
     tv[q] = (ok && a.T) ? ld_stream<NT_ADJ_LD>(a.T + gp) : 0.0;
     lv[q] = (ok && !lt && !a.lam_is_x && a.lam) ? ld_stream<NT_ADJ_LD>(a.lam + gp) : 0.0;
     cv[q] = (ok && !lt && a.laccsrc) ? ld_stream<NT_ADJ_LD>(a.laccsrc + gp) : 0.0;
+  }
+  const bool need_red = !lt && (grads || d.scattering);
+  if constexpr (RED_STAGED) {
+    if (need_red) {
+#pragma unroll
+      for (int pl = 0; pl < C::NPW; ++pl) {
+        const double v0 = plane_rows_sum<64>(ru[pl]), v1 = plane_rows_sum<64>(ruy[pl]),
+                     v2 = plane_rows_sum<64>(rwy[pl]);
+        if ((tid & 63) == 0) {
+          sRedW[tid >> 6][pl][0] = v0;
+          sRedW[tid >> 6][pl][1] = v1;
+          sRedW[tid >> 6][pl][2] = v2;
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -708,23 +767,24 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4)
     const int pl = lane / C::LPP, li = lane % C::LPP;
     const bool isTh = li < NT;
     const LineMap<NT> lm = line_map<NT>(pl, li);
-    const int64_t pid = plane0 + pl;
-    const PlaneIdx pi = plane_index(d, pid < npl ? pid : 0);
-    const double inv_r = t.inv_r[pi.j], cot_th = t.cot_th[pi.l];
-    if (part == 0 && !isTh && !lt) {
-      const int i = li - NT;
-      double su = 0.0, suy = 0.0, sy = 0.0;
-      for (int q = 0; q < C::L; ++q) {
-        const int ix = lm.idx(q);
-        su += sU[ix];
-        if (grads) {
-          suy += sU[ix] * sY[ix];
-          sy += sY[ix];
+    const double inv_r = sPA[pl].inv_r, cot_th = sPA[pl].cot_th;
+    if constexpr (!RED_STAGED) {
+      if (part == 0 && !isTh && !lt) {
+        // row sums of u, u Y_s and w Y_s of each Phi row (summed per plane below)
+        const int i = li - NT;
+        double su = 0.0, suy = 0.0, sy = 0.0;
+        for (int q = 0; q < C::L; ++q) {
+          const int ix = lm.idx(q);
+          su += sU[ix];
+          if (grads) {
+            suy += sU[ix] * sY[ix];
+            sy += sY[ix];
+          }
         }
+        sRed[pl * NT + i][0] = su;
+        sRed[pl * NT + i][1] = suy;
+        sRed[pl * NT + i][2] = sWm[i] * sy;
       }
-      sRed[pl * NT + i][0] = su;
-      sRed[pl * NT + i][1] = suy;
-      sRed[pl * NT + i][2] = t.wmean[i] * sy;
     }
     if constexpr (AN) if (part == 0) {
       // unweighted moments of u (for K^T u) and weighted moments of Y_s (for the
@@ -739,7 +799,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4)
         row_moments(1.0, sCT[i], sTh[i], S0, C1, S1, C2, S2, mu);
         if (grads) {
           row_fourier<C::NF>(sCP, sPh, [&](int q) { return sY[lm.idx(q)]; }, S0, C1, S1, C2, S2);
-          row_moments(t.wmean[i], sCT[i], sTh[i], S0, C1, S1, C2, S2, my);
+          row_moments(sWm[i], sCT[i], sTh[i], S0, C1, S1, C2, S2, my);
         }
       }
 #pragma unroll
@@ -760,8 +820,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4)
       const bool th = (part & 1) == 0;
       const int lr = lane & 15, lk = lane >> 4;
       const int pb = mp * C::PS;
-      const PlaneIdx pm = plane_index(d, plane0 + mp < npl ? plane0 + mp : 0);
-      const double ir = t.inv_r[pm.j], ct = t.cot_th[pm.l];
+      const double ir = sPA[mp].inv_r, ct = sPA[mp].cot_th;
       v4d cp = {0.0, 0.0, 0.0, 0.0}, cq = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 1
       for (int k = 0; k < NT / 4; ++k) {
@@ -802,12 +861,24 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4)
   }
   __syncthreads();
 
+  // plane sums of u for K^T u (isotropic, staged reduction): the wavefronts'
+  // partial sums in a fixed order
+  double psu[RED_STAGED ? C::NPW : 1];
+  if constexpr (RED_STAGED) {
+#pragma unroll
+    for (int pl = 0; pl < C::NPW; ++pl) {
+      psu[pl] = 0.0;
+      if (need_red) {
+#pragma unroll
+        for (int w = 0; w < C::NW; ++w) psu[pl] += sRedW[w][pl][0];
+      }
+    }
+  }
 #pragma unroll
   for (int q = 0; q < C::PPT; ++q) {
     const int p = tid + q * C::NTHR;
     const int pl = p / C::PLANE;
-    const int64_t pid = plane0 + pl;
-    if (pid >= npl) continue;
+    if (plane0 + pl >= npl) continue;
     const int64_t gp = gbase + p;
     const int lp = C::lds(p);
     const double LTu = tv[q] + sR[0][lp] + sR[1][lp];
@@ -817,21 +888,22 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4)
     }
     const double u = sU[lp];
     const int iTh = (p % C::PLANE) / C::NF;
-    double av = -LTu - cf.kappa[pid] * u;
+    double av = -LTu - sPA[pl].kappa * u;
     if (d.scattering) {
       // K^T u at this direction: w(omega') times the phase-weighted sums of u
       double ktu;
       if constexpr (AN) {
         const int m = p % C::NF;
-        ktu = t.wmean[iTh] * phase_contract(cf, sMoU[pl], sCT[iTh], sTh[iTh] * sCP[m], sTh[iTh] * sPh[m]);
+        ktu = sWm[iTh] * phase_contract(cf, sMoU[pl], sCT[iTh], sTh[iTh] * sCP[m], sTh[iTh] * sPh[m]);
+      } else if constexpr (RED_STAGED) {
+        ktu = sWm[iTh] * psu[(q * C::NTHR) / C::PLANE];
       } else {
         double su = 0.0;
 #pragma unroll
         for (int ii = 0; ii < NT; ++ii) su += sRed[pl * NT + ii][0];
-        ktu = t.wmean[iTh] * su;
+        ktu = sWm[iTh] * su;
       }
-      const double si = cf.sigma[pid];
-      av += si * (ktu - u);
+      av += sPA[pl].sigma * (ktu - u);
     }
     const double lam = a.lam_is_x ? xr[q] : lv[q];
     if (a.laccdst) st_stream<NT_ADJ_ST>(a.laccdst + gp, (a.laccsrc ? cv[q] : lam) + av);
@@ -840,13 +912,22 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4)
 
   if (grads && tid < C::NPW) {
     const int pl = tid;
-    const int64_t pid = plane0 + pl;
+    const int pid = plane0 + pl;
     if (pid < npl) {
       double su = 0.0, suy = 0.0, my = 0.0;
-      for (int ii = 0; ii < NT; ++ii) {
-        su += sRed[pl * NT + ii][0];
-        suy += sRed[pl * NT + ii][1];
-        my += sRed[pl * NT + ii][2];
+      if constexpr (RED_STAGED) {
+#pragma unroll
+        for (int w = 0; w < C::NW; ++w) {
+          su += sRedW[w][pl][0];
+          suy += sRedW[w][pl][1];
+          my += sRedW[w][pl][2];
+        }
+      } else {
+        for (int ii = 0; ii < NT; ++ii) {
+          su += sRed[pl * NT + ii][0];
+          suy += sRed[pl * NT + ii][1];
+          my += sRed[pl * NT + ii][2];
+        }
       }
       if (a.gk) a.gk[pid] -= suy;
       if (a.ge) a.ge[pid] += su;
