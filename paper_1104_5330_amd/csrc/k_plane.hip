@@ -643,8 +643,8 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
 //   (K = avg for isotropic scattering: sum u (K Y_s) = <Y_s> sum u)
 // Transposed line: v_q = coef_q u_q; z = D v; result_q = -z_q (D^T = -D).
 
-// four waves per SIMD (128 VGPRs): measured 10 % faster per adjoint step than
-// three
+// four waves per SIMD: measured 10 % faster per adjoint step than three; the
+// isotropic 16 x 32 instance takes 102 VGPRs (at five waves it spills, for 0.4 %)
 template <int NT, bool AN>
 __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(4))) void k_plane_adj(KDims d, KTab t, KCoef cf, AdjArgs a,
                                                             double* lt_out) {
