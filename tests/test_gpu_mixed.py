@@ -46,7 +46,8 @@ def make(cfg, **kw):
     small(3, n_eps=1, n_r=5, n_theta=4, n_phi=8, n_Theta=32, n_Phi=64),
     small(3, n_eps=2, n_r=5, n_theta=32, n_phi=64, n_Theta=8, n_Phi=16),
     small(5, n_eps=1, n_r=3),
-], ids=["tiny", "small", "w3_r33", "r65", "wide_plane", "sphere64", "w5_slab"])
+    small(3, n_eps=1, n_r=80, n_theta=2, n_phi=4, n_Theta=4, n_Phi=8),
+], ids=["tiny", "small", "w3_r33", "r65", "wide_plane", "sphere64", "w5_slab", "r80"])
 def test_mixed_terms_and_rhs(cfg):
     G = make(cfg)
     F = synth.fields.shell_state(cfg)
