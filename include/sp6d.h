@@ -24,7 +24,8 @@
  * Conventions shared by every entry point:
  *   - States are FP64 device arrays in C order [eps][r][theta][phi][Theta][Phi]
  *     (Phi fastest), owned by the caller, 16-byte aligned, never aliased with
- *     another array argument of the same call.
+ *     another array argument of the same call, and (device memory) on the
+ *     handle's GPU.
  *   - Coefficient fields (kappa, sigma, eta, gradients) are FP64 device arrays
  *     [eps][r][theta][phi] (isotropic, one value per (Theta, Phi) plane).
  *   - All device work is enqueued on the handle's HIP stream; only

@@ -143,7 +143,7 @@ sp6_status check_grid(sp6_grid g) {
 // allocator hands out parts of larger allocations, so a buffer that is too
 // short but followed by more of its allocation is not detected; one that runs
 // past the allocation's end is.)
-sp6_status check_dev(const void* p, size_t bytes, const char* name) {
+sp6_status check_dev(sp6_grid g, const void* p, size_t bytes, const char* name) {
   if (!p) return fail(SP6_ERR_ARG, std::string(name) + " is NULL");
   if (reinterpret_cast<uintptr_t>(p) % 16 != 0) return fail(SP6_ERR_ARG, std::string(name) + " is not 16-byte aligned");
   hipPointerAttribute_t attr;
@@ -155,6 +155,9 @@ sp6_status check_dev(const void* p, size_t bytes, const char* name) {
   }
   if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged && attr.type != hipMemoryTypeUnified)
     return fail(SP6_ERR_ARG, std::string(name) + " is not device memory");
+  if (attr.type == hipMemoryTypeDevice && attr.device != g->device)
+    return fail(SP6_ERR_ARG, std::string(name) + " is on device " + std::to_string(attr.device) +
+                                 ", the handle on device " + std::to_string(g->device));
   hipDeviceptr_t base = nullptr;
   size_t size = 0;
   e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
@@ -315,9 +318,9 @@ sp6_status fp64_rhs_like(sp6_grid g, const double* F, double* out, int mode, uin
 
 sp6_status check_state_io(sp6_grid g, const void* in, const char* nin, const void* out, const char* nout) {
   const size_t B = state_bytes(g);
-  sp6_status s = check_dev(in, B, nin);
+  sp6_status s = check_dev(g, in, B, nin);
   if (s) return s;
-  s = check_dev(out, B, nout);
+  s = check_dev(g, out, B, nout);
   if (s) return s;
   return check_distinct(in, nin, out, nout, B, B);
 }
@@ -502,9 +505,9 @@ sp6_status sp6_get_weights(sp6_grid g, double* w_r, double* w_theta, double* w_p
 sp6_status sp6_set_coefficients(sp6_grid g, const double* kappa, const double* sigma, const double* eta) {
   if (sp6_status s = check_grid(g)) return s;
   const size_t cb = size_t(g->d.nplanes) * sizeof(double);
-  if (sp6_status s = check_dev(kappa, cb, "kappa")) return s;
-  if (sp6_status s = check_dev(sigma, cb, "sigma")) return s;
-  if (sp6_status s = check_dev(eta, cb, "eta")) return s;
+  if (sp6_status s = check_dev(g, kappa, cb, "kappa")) return s;
+  if (sp6_status s = check_dev(g, sigma, cb, "sigma")) return s;
+  if (sp6_status s = check_dev(g, eta, cb, "eta")) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   HIP_TRY(hipMemcpyAsync(g->kappa, kappa, cb, hipMemcpyDeviceToDevice, g->stream), "copy kappa");
   HIP_TRY(hipMemcpyAsync(g->sigma, sigma, cb, hipMemcpyDeviceToDevice, g->stream), "copy sigma");
@@ -535,9 +538,9 @@ sp6_status sp6_set_inflow(sp6_grid g, const double* g_in, const double* g_out) {
   if (sp6_status s = check_grid(g)) return s;
   const size_t gb = size_t(g->d.n_eps) * g->d.M * sizeof(double);
   if (g_in)
-    if (sp6_status s = check_dev(g_in, gb, "g_in")) return s;
+    if (sp6_status s = check_dev(g, g_in, gb, "g_in")) return s;
   if (g_out)
-    if (sp6_status s = check_dev(g_out, gb, "g_out")) return s;
+    if (sp6_status s = check_dev(g, g_out, gb, "g_out")) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   if (g_in)
     HIP_TRY(hipMemcpyAsync(g->g_in, g_in, gb, hipMemcpyDeviceToDevice, g->stream), "copy g_in");
@@ -552,7 +555,7 @@ sp6_status sp6_set_inflow(sp6_grid g, const double* g_in, const double* g_out) {
 
 sp6_status sp6_project_inflow(sp6_grid g, double* F) {
   if (sp6_status s = check_grid(g)) return s;
-  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  if (sp6_status s = check_dev(g, F, state_bytes(g), "F")) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   HIP_TRY(launch_project(g->d, g->t, g->c, F, g->stream), "project inflow");
   return SP6_OK;
@@ -588,7 +591,7 @@ sp6_status sp6_rhs(sp6_grid g, const double* F, double* out) {
 
 sp6_status sp6_apply_filter(sp6_grid g, double* F) {
   if (sp6_status s = check_grid(g)) return s;
-  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  if (sp6_status s = check_dev(g, F, state_bytes(g), "F")) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   HIP_TRY(launch_filter(g->d, g->t, F, g->desc.filter == 2 ? 1 : 0, g->stream), "filter");
   return SP6_OK;
@@ -658,7 +661,7 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
   if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
   if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
-  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  if (sp6_status s = check_dev(g, F, state_bytes(g), "F")) return s;
   if (nsteps == 0) return SP6_OK;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   const bool mixed = g->desc.precision == SP6_MIXED;
@@ -774,8 +777,8 @@ sp6_status sp6_step_stages(sp6_grid g, double* F, double dt, double* Ystages) {
   if (sp6_status s = check_grid(g)) return s;
   if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "sp6_step_stages needs an FP64 handle");
   const size_t B = state_bytes(g);
-  if (sp6_status s = check_dev(F, B, "F")) return s;
-  if (sp6_status s = check_dev(Ystages, 3 * B, "Ystages")) return s;
+  if (sp6_status s = check_dev(g, F, B, "F")) return s;
+  if (sp6_status s = check_dev(g, Ystages, 3 * B, "Ystages")) return s;
   if (sp6_status s = check_distinct(F, "F", Ystages, "Ystages", B, 3 * B)) return s;
   return run_steps(g, F, dt, 1, nullptr, false, Ystages);
 }
@@ -859,7 +862,7 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
   if (sp6_status s = check_state_io(g, Fn, "F_n", lam, "lam")) return s;
   if (Ystages) {
     const size_t B3 = 3 * state_bytes(g);
-    if (sp6_status s = check_dev(Ystages, B3, "Ystages")) return s;
+    if (sp6_status s = check_dev(g, Ystages, B3, "Ystages")) return s;
     if (sp6_status s = check_distinct(Ystages, "Ystages", Fn, "F_n", B3, state_bytes(g))) return s;
     if (sp6_status s = check_distinct(Ystages, "Ystages", lam, "lam", B3, state_bytes(g))) return s;
   }
@@ -868,7 +871,7 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
   const char* gn[3] = {"grad_kappa", "grad_eta", "grad_sigma"};
   for (int i = 0; i < 3; ++i) {
     if (!gr[i]) continue;
-    if (sp6_status s = check_dev(gr[i], cb, gn[i])) return s;
+    if (sp6_status s = check_dev(g, gr[i], cb, gn[i])) return s;
     if (sp6_status s = check_distinct(gr[i], gn[i], Fn, "F_n", cb, state_bytes(g))) return s;
     if (sp6_status s = check_distinct(gr[i], gn[i], lam, "lam", cb, state_bytes(g))) return s;
     for (int j = 0; j < i; ++j)
@@ -956,7 +959,7 @@ sp6_status sp6_adjoint_step_stages(sp6_grid g, const double* Fn, const double* Y
 
 sp6_status sp6_diagnostics(sp6_grid g, const double* F, double* N, double* J_in, double* J_out) {
   if (sp6_status s = check_grid(g)) return s;
-  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  if (sp6_status s = check_dev(g, F, state_bytes(g), "F")) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   const double rin = g->h.r.front(), rout = g->h.r.back();
   HIP_TRY(launch_diag(g->d, g->t, F, g->diag_partial, rin * rin, rout * rout, g->diag_out, g->stream), "diagnostics");
@@ -974,9 +977,9 @@ sp6_status sp6_diagnostics(sp6_grid g, const double* F, double* N, double* J_in,
 
 sp6_status sp6_outgoing_flux(sp6_grid g, const double* F, double* j) {
   if (sp6_status s = check_grid(g)) return s;
-  if (sp6_status s = check_dev(F, state_bytes(g), "F")) return s;
+  if (sp6_status s = check_dev(g, F, state_bytes(g), "F")) return s;
   const size_t jb = size_t(g->d.n_eps) * g->d.n_th * g->d.n_ph * sizeof(double);
-  if (sp6_status s = check_dev(j, jb, "j")) return s;
+  if (sp6_status s = check_dev(g, j, jb, "j")) return s;
   if (sp6_status s = check_distinct(F, "F", j, "j", state_bytes(g), jb)) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   HIP_TRY(launch_outflux(g->d, g->t, F, j, g->stream), "outgoing flux");
@@ -986,8 +989,8 @@ sp6_status sp6_outgoing_flux(sp6_grid g, const double* F, double* j) {
 sp6_status sp6_outgoing_flux_T(sp6_grid g, const double* jbar, double* out) {
   if (sp6_status s = check_grid(g)) return s;
   const size_t jb = size_t(g->d.n_eps) * g->d.n_th * g->d.n_ph * sizeof(double);
-  if (sp6_status s = check_dev(jbar, jb, "jbar")) return s;
-  if (sp6_status s = check_dev(out, state_bytes(g), "out")) return s;
+  if (sp6_status s = check_dev(g, jbar, jb, "jbar")) return s;
+  if (sp6_status s = check_dev(g, out, state_bytes(g), "out")) return s;
   if (sp6_status s = check_distinct(jbar, "jbar", out, "out", jb, state_bytes(g))) return s;
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   HIP_TRY(launch_outflux_T(g->d, g->t, jbar, out, g->stream), "outgoing flux transpose");
