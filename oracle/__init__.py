@@ -21,7 +21,9 @@ equation by the use of 6D spectral methods in spherical coordinates"):
   (Eq. Sphedif);
 * classical RK4 in time, its discrete adjoint, an optional exponential
   filter and the particle-number / flux diagnostics of App. A (Eqs. Npho,
-  Flux, Cons).
+  Flux, Cons);
+* optionally, the Fokker-Planck energy coupling of Sect. 3.2 (Eq. Transpfp)
+  on a Chebyshev energy axis (energy.py).
 
 Every 1D transform is an explicit dense matrix applied along one axis, with no
 FFT, no blocking and no fusion, so that each function can be checked against
@@ -30,4 +32,4 @@ listed in each function's docstring.
 """
 
 from .grid import Grid, make_grid  # noqa: F401
-from . import ops, step, adjoint, diagnostics, closed_forms, conservative  # noqa: F401
+from . import ops, step, adjoint, diagnostics, closed_forms, conservative, energy  # noqa: F401

@@ -17,7 +17,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import ops
+from . import energy, ops
 
 
 @dataclass
@@ -41,6 +41,9 @@ class Physics:
     # re-imposed after the filter
     g_in: np.ndarray = None
     g_out: np.ndarray = None
+    # Fokker-Planck energy coupling (energy.fp_source) as (gamma_min, gamma_max,
+    # alpha), the groups being the Chebyshev nodes of gamma; None = off
+    energy: tuple = None
 
     @staticmethod
     def vacuum(g, bc=True):
@@ -58,7 +61,11 @@ def filter_step(y, g, p):
 
 
 def rhs(F, g, p):
-    return ops.rhs(F, g, p.kappa, p.sigma, p.eta, bc=p.bc, scattering=p.scattering, kernel=p.kernel,
+    eta = p.eta
+    if p.energy is not None:
+        s = p.sigma if p.scattering else np.zeros_like(np.asarray(p.sigma, np.float64))
+        eta = np.asarray(p.eta, np.float64) + energy.fp_source(F, g, s, *p.energy)
+    return ops.rhs(F, g, p.kappa, p.sigma, eta, bc=p.bc, scattering=p.scattering, kernel=p.kernel,
                    radial=not p.radial_implicit)
 
 
