@@ -127,6 +127,30 @@ sp6_status sp6_set_coefficients(sp6_grid grid, const double* kappa, const double
  * previous kernel then. */
 sp6_status sp6_set_scattering_kernel(sp6_grid grid, double c1, double c2);
 
+/* Fokker-Planck energy coupling (Sect. 3.2, Eq. Transpfp).  enable = 1: the n_eps
+ * energy groups are taken as the Chebyshev-Gauss-Lobatto nodes gamma_k of
+ * [gamma_min, gamma_max] (ascending, k = 0 first), and every right-hand side of
+ * sp6_rhs and the RK4 steps (sp6_step, _stages, _noalloc, _timed,
+ * _radial_implicit) gains, per (eps, r, theta, phi) plane, the isotropic source
+ *   sigma S,  S = (1/4pi) d/dgamma [alpha gamma^2 dM0/dgamma + (gamma^2 - 2 alpha gamma) M0]
+ *               + 3/(128 pi^2) dQ/dgamma,
+ *   M0 = int F dw,  Q = int int (1 - mu + mu^2 - mu^3) F(w') F(w'') dw' dw'',
+ * gamma derivatives by Chebyshev collocation across the groups, angular integrals
+ * by the plane quadrature (Fejer in cos Theta, uniform in Phi).  sigma is the
+ * handle's scattering coefficient (n sigma_Th); with the Thomson kernel
+ * (sp6_set_scattering_kernel(grid, 0, 0.75)) the right-hand side is Eq.
+ * (Transpfp).  The sign is the one for which the energy diffusion runs forward
+ * and the Bose distribution of Eq. (Bose) is steady; the printed Eq. (Kompa) has
+ * the opposite overall sign.  The source is added to eta, so it is zero at the
+ * inflow nodes with the rest of the right-hand side.  Nonlinear in F: while it is
+ * on, sp6_adjoint_step(_stages) and sp6_step_ab2 return SP6_ERR_STATE.
+ * enable = 0 turns it off (the other arguments are ignored).  Needs an FP64
+ * handle created with scattering = 1 (SP6_ERR_STATE), 2 <= n_eps <= 64
+ * (SP6_ERR_SHAPE), 0 <= gamma_min < gamma_max and alpha >= 0, finite
+ * (SP6_ERR_ARG).  Allocates three per-plane device arrays on first use. */
+sp6_status sp6_set_energy_coupling(sp6_grid grid, int32_t enable, double gamma_min, double gamma_max,
+                                   double alpha);
+
 /* Inflow planes [n_eps][n_theta][n_phi][n_Theta][n_Phi] at r_in and r_out (device);
  * only the incoming half (cos Theta > 0 at r_in, < 0 at r_out) is used.
  * NULL sets that plane to zero. */
@@ -182,8 +206,8 @@ sp6_status sp6_step_ab2(sp6_grid grid, double* F, double* H, double dt, int32_t 
  * of launches of kernel class c: 0 phi pass, 1 theta pass, 2 radial pass, 3 plane
  * pass (Theta, Phi, collision, inflow, RK stage), 4 filter, 5 theta and phi
  * passes fused into one (used when n_phi = 2 n_theta <= 32, and for n_theta = 32,
- * n_phi = 64, n_Phi >= 16).  Both arrays are host arrays of 6 entries.  For
- * measurement only. */
+ * n_phi = 64, n_Phi >= 16), 6 energy-coupling source (sp6_set_energy_coupling).
+ * Both arrays are host arrays of 7 entries.  For measurement only. */
 sp6_status sp6_step_timed(sp6_grid grid, double* F, double dt, int32_t nsteps, double* kernel_ms,
                           int64_t* launches);
 

@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "SP6_OK", 1: "SP6_ERR_ARG", 2: "SP6_ERR_SHAPE", 3: "SP6_ERR_A
 # the exported entry points, in header order
 SYMBOLS = [
     "sp6_validate_desc", "sp6_create", "sp6_destroy", "sp6_set_stream", "sp6_last_error",
-    "sp6_get_nodes", "sp6_get_weights", "sp6_set_coefficients", "sp6_set_scattering_kernel", "sp6_set_inflow",
+    "sp6_get_nodes", "sp6_get_weights", "sp6_set_coefficients", "sp6_set_scattering_kernel", "sp6_set_energy_coupling",
+    "sp6_set_inflow",
     "sp6_project_inflow", "sp6_apply_L", "sp6_apply_L_terms", "sp6_apply_LT", "sp6_rhs",
     "sp6_step", "sp6_step_stages", "sp6_adjoint_step_stages", "sp6_step_radial_implicit", "sp6_step_ab2", "sp6_step_timed", "sp6_adjoint_step", "sp6_apply_filter", "sp6_diagnostics",
     "sp6_outgoing_flux", "sp6_outgoing_flux_T", "sp6_step_noalloc", "sp6_device_bytes",
@@ -66,6 +67,7 @@ def load():
         "sp6_get_weights": (S, [P, dp, dp, dp, dp, dp]),
         "sp6_set_coefficients": (S, [P, P, P, P]),
         "sp6_set_scattering_kernel": (S, [P, D, D]),
+        "sp6_set_energy_coupling": (S, [P, I32, D, D, D]),
         "sp6_set_inflow": (S, [P, P, P]),
         "sp6_project_inflow": (S, [P, P]),
         "sp6_apply_L": (S, [P, P, P]),

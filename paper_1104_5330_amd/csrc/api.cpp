@@ -75,6 +75,15 @@ struct sp6_grid_s {
   double imp_dt = 0.0;
   // device address of the fixed scratch of sp6_step_noalloc on this device
   void* noalloc = nullptr;
+  // Fokker-Planck energy coupling: energy-node derivative [n_eps][n_eps] and
+  // nodes, (M0, Q) per plane, and the emissivity with the source added
+  bool fp_on = false;
+  double fp_alpha = 0.0;
+  double* fp_D = nullptr;
+  double* fp_gam = nullptr;
+  double* fp_mq = nullptr;
+  double* fp_eta = nullptr;
+  std::vector<double> fp_host;  // host copy of D and the nodes (source of the uploads)
 
   hipError_t alloc(void** p, size_t n) {
     hipError_t e = hipMalloc(p, n);
@@ -203,7 +212,7 @@ struct Timer {
   }
 };
 
-enum { KC_PHI = 0, KC_THETA = 1, KC_RADIAL = 2, KC_PLANE = 3, KC_FILTER = 4, KC_SPHERE = 5, KC_COUNT = 6 };
+enum { KC_PHI = 0, KC_THETA = 1, KC_RADIAL = 2, KC_PLANE = 3, KC_FILTER = 4, KC_SPHERE = 5, KC_ENERGY = 6, KC_COUNT = 7 };
 
 hipError_t ensure(sp6_grid g, double** p, size_t n) {
   if (*p) return hipSuccess;
@@ -293,6 +302,18 @@ hipError_t ensure_f32(sp6_grid g, float** p) {
   return g->alloc(reinterpret_cast<void**>(p), size_t(g->d.P) * sizeof(float));
 }
 
+// The coefficients of a right-hand side of the stage input Y: the handle's, or
+// with the energy coupling on, with eta + sigma S(Y) as the emissivity
+hipError_t rhs_coefs(sp6_grid g, const double* Y, KCoef* c, Timer* tm = nullptr) {
+  *c = g->c;
+  if (!g->fp_on) return hipSuccess;
+  hipError_t e = launch_fp_source(g->d, g->t, Y, g->fp_D, g->fp_gam, g->fp_alpha, g->fp_mq, g->eta, g->sigma,
+                                  g->fp_eta, g->stream);
+  if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_ENERGY);
+  c->eta = g->fp_eta;
+  return e;
+}
+
 sp6_status fp64_rhs_like(sp6_grid g, const double* F, double* out, int mode, uint32_t terms) {
   HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
   const bool mixed = g->desc.precision == SP6_MIXED;
@@ -312,7 +333,9 @@ sp6_status fp64_rhs_like(sp6_grid g, const double* F, double* out, int mode, uin
   a.T = wrote ? (mixed ? static_cast<const void*>(g->Tf) : static_cast<const void*>(g->T)) : nullptr;
   a.out = out;
   a.terms = terms;
-  HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
+  KCoef c = g->c;
+  if (mode == PM_RHS) HIP_TRY(rhs_coefs(g, F, &c), "energy coupling");
+  HIP_TRY(launch_plane(next_pass(g), g->t, c, a, g->stream), "plane pass");
   return SP6_OK;
 }
 
@@ -534,6 +557,40 @@ sp6_status sp6_set_scattering_kernel(sp6_grid g, double c1, double c2) {
   return SP6_OK;
 }
 
+sp6_status sp6_set_energy_coupling(sp6_grid g, int32_t enable, double gamma_min, double gamma_max, double alpha) {
+  if (sp6_status s = check_grid(g)) return s;
+  if (!enable) {
+    g->fp_on = false;
+    return SP6_OK;
+  }
+  if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "the energy coupling needs an FP64 handle");
+  if (!g->desc.scattering) return fail(SP6_ERR_STATE, "the energy coupling needs scattering = 1 (its source scales with sigma)");
+  const int n = g->desc.n_eps;
+  if (n < 2 || n > 64) return fail(SP6_ERR_SHAPE, "the energy coupling needs 2 <= n_eps <= 64 (Chebyshev nodes of gamma)");
+  if (!(gamma_min >= 0.0) || !(gamma_max > gamma_min) || !std::isfinite(gamma_max))
+    return fail(SP6_ERR_ARG, "need 0 <= gamma_min < gamma_max, finite");
+  if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(SP6_ERR_ARG, "alpha must be finite and >= 0");
+  HIP_TRY(hipSetDevice(g->device), "hipSetDevice");
+  const size_t pb = size_t(g->d.nplanes) * sizeof(double);
+  HIP_TRY(ensure(g, &g->fp_D, size_t(n) * n * sizeof(double)), "allocate energy tables");
+  HIP_TRY(ensure(g, &g->fp_gam, size_t(n) * sizeof(double)), "allocate energy tables");
+  HIP_TRY(ensure(g, &g->fp_mq, 2 * pb), "allocate energy scratch");
+  HIP_TRY(ensure(g, &g->fp_eta, pb), "allocate energy scratch");
+  // the previous upload may still be in flight from the host copy
+  HIP_TRY(hipStreamSynchronize(g->stream), "synchronise");
+  g->fp_host = cgl_derivative(n, gamma_min, gamma_max);
+  const std::vector<double> gam = cgl_nodes(n, gamma_min, gamma_max);
+  g->fp_host.insert(g->fp_host.end(), gam.begin(), gam.end());
+  HIP_TRY(hipMemcpyAsync(g->fp_D, g->fp_host.data(), size_t(n) * n * sizeof(double), hipMemcpyHostToDevice, g->stream),
+          "upload energy tables");
+  HIP_TRY(hipMemcpyAsync(g->fp_gam, g->fp_host.data() + size_t(n) * n, size_t(n) * sizeof(double),
+                         hipMemcpyHostToDevice, g->stream),
+          "upload energy tables");
+  g->fp_alpha = alpha;
+  g->fp_on = true;
+  return SP6_OK;
+}
+
 sp6_status sp6_set_inflow(sp6_grid g, const double* g_in, const double* g_out) {
   if (sp6_status s = check_grid(g)) return s;
   const size_t gb = size_t(g->d.n_eps) * g->d.M * sizeof(double);
@@ -727,7 +784,9 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
           a.ysrc = nullptr, a.ynext = nullptr, a.cn = 0.0;
           break;
       }
-      HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
+      KCoef c = g->c;
+      if (!mixed) HIP_TRY(rhs_coefs(g, static_cast<const double*>(a.Yin), &c, tm), "energy coupling");
+      HIP_TRY(launch_plane(next_pass(g), g->t, c, a, g->stream), "plane pass");
       if (tm) HIP_TRY(tm->mark(g->stream, KC_PLANE), "event");
     }
     if (radial_implicit) {
@@ -793,6 +852,7 @@ sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nst
   if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
   if (start != 0 && start != 1) return fail(SP6_ERR_ARG, "start must be 0 or 1");
   if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "sp6_step_ab2 needs an FP64 handle");
+  if (g->fp_on) return fail(SP6_ERR_STATE, "sp6_step_ab2 does not take the energy coupling (sp6_set_energy_coupling)");
   if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
   if (sp6_status s = check_state_io(g, F, "F", H, "H")) return s;
   if (nsteps == 0) return SP6_OK;
@@ -857,6 +917,7 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
                         double* ge, double* gs) {
   if (sp6_status s = check_grid(g)) return s;
   if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "adjoint_step is FP64-only");
+  if (g->fp_on) return fail(SP6_ERR_STATE, "adjoint_step is not defined with the energy coupling (nonlinear)");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
   if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
   if (sp6_status s = check_state_io(g, Fn, "F_n", lam, "lam")) return s;

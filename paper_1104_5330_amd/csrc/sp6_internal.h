@@ -81,6 +81,10 @@ struct HostTables {
 };
 
 void build_host_tables(const sp6_desc& d, HostTables& t);
+// Chebyshev-Gauss-Lobatto nodes of [a, b] (ascending) and their collocation
+// derivative matrix (n x n, row major)
+std::vector<double> cgl_nodes(int n, double a, double b);
+std::vector<double> cgl_derivative(int n, double a, double b);
 // [4][2728]: derivative, filter, and the transposes of both, for every supported
 // line length (even/odd form)
 std::vector<double> build_line_tables();
@@ -152,6 +156,12 @@ hipError_t launch_plane_adj(const KDims& d, const KTab& t, const KCoef& c, const
                             hipStream_t s);
 hipError_t launch_plane_LT(const KDims& d, const KTab& t, const double* G, const double* T,
                            double* out, hipStream_t s);
+
+// Fokker-Planck energy coupling: (M0, Q) of every plane of Y into mq, then
+// eta_eff = eta + sigma S per plane (D: energy-node derivative, gam: nodes)
+hipError_t launch_fp_source(const KDims& d, const KTab& t, const double* Y, const double* D, const double* gam,
+                            double alpha, double* mq, const double* eta, const double* sigma, double* eta_eff,
+                            hipStream_t s);
 
 // filter, projection, diagnostics
 // the angular line filters, then (radial = 1) the radial filter or (radial = 2)

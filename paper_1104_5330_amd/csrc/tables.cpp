@@ -133,12 +133,50 @@ std::string validate_desc(const sp6_desc& d, sp6_status* code) {
   return "";
 }
 
+std::vector<double> cgl_nodes(int n, double a, double b) {
+  std::vector<double> x(n);
+  for (int j = 0; j < n; ++j) x[j] = 0.5 * (a + b) - 0.5 * (b - a) * std::cos(M_PI * j / (n - 1));
+  return x;
+}
+
+// Chebyshev-Gauss-Lobatto derivative, ascending nodes.  Off-diagonal entries
+// (c_i / c_j) (-1)^(i+j) / (x_i - x_j) with the node difference in product form
+// 2 sin(pi (i+j) / 2N) sin(pi (i-j) / 2N); the matrix is made exactly
+// centro-antisymmetric and its diagonal is minus the off-diagonal row sum.
+std::vector<double> cgl_derivative(int n, double a, double b) {
+  const int N = n - 1;
+  std::vector<double> D(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      if (i == j) continue;
+      double ci = (i == 0 || i == N) ? 2.0 : 1.0, cj = (j == 0 || j == N) ? 2.0 : 1.0;
+      double dx = 2.0 * std::sin(M_PI * (i + j) / (2.0 * N)) * std::sin(M_PI * (i - j) / (2.0 * N));
+      double sgn = ((i + j) & 1) ? -1.0 : 1.0;
+      D[size_t(i) * n + j] = (ci / cj) * sgn / dx;
+    }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      if (i == j || i * n + j > (N - i) * n + (N - j)) continue;  // each mirror pair once
+      double p = D[size_t(i) * n + j], q = D[size_t(N - i) * n + (N - j)];
+      double v = 0.5 * (p - q);
+      D[size_t(i) * n + j] = v;
+      D[size_t(N - i) * n + (N - j)] = -v;
+    }
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j)
+      if (j != i) s += D[size_t(i) * n + j];
+    D[size_t(i) * n + i] = -s;
+  }
+  const double scale = 2.0 / (b - a);
+  for (auto& v : D) v *= scale;
+  return D;
+}
+
 void build_host_tables(const sp6_desc& d, HostTables& t) {
   const int nr = d.n_r, nth = d.n_theta, nph = d.n_phi, nTh = d.n_Theta, nPh = d.n_Phi;
   const int N = nr - 1;
-  t.r.resize(nr);
-  for (int j = 0; j < nr; ++j)
-    t.r[j] = 0.5 * (d.r_in + d.r_out) - 0.5 * (d.r_out - d.r_in) * std::cos(M_PI * j / N);
+  t.r = cgl_nodes(nr, d.r_in, d.r_out);
   t.theta.resize(nth);
   for (int l = 0; l < nth; ++l) t.theta[l] = (l + 0.5) * M_PI / nth;
   t.phi.resize(nph);
@@ -156,36 +194,7 @@ void build_host_tables(const sp6_desc& d, HostTables& t) {
   t.w_ph.assign(nph, 2.0 * M_PI / nph);
   t.w_Ph.assign(nPh, 2.0 * M_PI / nPh);
 
-  // Chebyshev-Gauss-Lobatto derivative, ascending nodes.  Off-diagonal entries
-  // (c_i / c_j) (-1)^(i+j) / (x_i - x_j) with the node difference in product form
-  // 2 sin(pi (i+j) / 2N) sin(pi (i-j) / 2N); the matrix is made exactly
-  // centro-antisymmetric and its diagonal is minus the off-diagonal row sum.
-  std::vector<double> D(size_t(nr) * nr, 0.0);
-  for (int i = 0; i < nr; ++i)
-    for (int j = 0; j < nr; ++j) {
-      if (i == j) continue;
-      double ci = (i == 0 || i == N) ? 2.0 : 1.0, cj = (j == 0 || j == N) ? 2.0 : 1.0;
-      double dx = 2.0 * std::sin(M_PI * (i + j) / (2.0 * N)) * std::sin(M_PI * (i - j) / (2.0 * N));
-      double sgn = ((i + j) & 1) ? -1.0 : 1.0;
-      D[size_t(i) * nr + j] = (ci / cj) * sgn / dx;
-    }
-  for (int i = 0; i < nr; ++i)
-    for (int j = 0; j < nr; ++j) {
-      if (i == j || i * nr + j > (N - i) * nr + (N - j)) continue;  // each mirror pair once
-      double a = D[size_t(i) * nr + j], b = D[size_t(N - i) * nr + (N - j)];
-      double v = 0.5 * (a - b);
-      D[size_t(i) * nr + j] = v;
-      D[size_t(N - i) * nr + (N - j)] = -v;
-    }
-  for (int i = 0; i < nr; ++i) {
-    double s = 0.0;
-    for (int j = 0; j < nr; ++j)
-      if (j != i) s += D[size_t(i) * nr + j];
-    D[size_t(i) * nr + i] = -s;
-  }
-  const double scale = 2.0 / (d.r_out - d.r_in);
-  for (auto& v : D) v *= scale;
-  t.Dr = D;
+  t.Dr = cgl_derivative(nr, d.r_in, d.r_out);
 
   t.NRP = ((nr + 15) / 16) * 16;
   t.KP = ((nr + 3) / 4) * 4;
@@ -193,8 +202,8 @@ void build_host_tables(const sp6_desc& d, HostTables& t) {
   t.DpadT.assign(size_t(t.NRP) * t.KP, 0.0);
   for (int i = 0; i < nr; ++i)
     for (int j = 0; j < nr; ++j) {
-      t.Dpad[size_t(i) * t.KP + j] = D[size_t(i) * nr + j];
-      t.DpadT[size_t(i) * t.KP + j] = D[size_t(j) * nr + i];
+      t.Dpad[size_t(i) * t.KP + j] = t.Dr[size_t(i) * nr + j];
+      t.DpadT[size_t(i) * t.KP + j] = t.Dr[size_t(j) * nr + i];
     }
 
   // radial filter: exp(-36 (k/N)^36) on the Chebyshev interpolant of an r line,

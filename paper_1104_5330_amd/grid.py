@@ -120,6 +120,12 @@ class Sp6Grid:
         (isotropic by default; Thomson is c1 = 0, c2 = 3/4)."""
         self._call(self.lib.sp6_set_scattering_kernel, ctypes.c_double(c1), ctypes.c_double(c2))
 
+    def set_energy_coupling(self, gamma_min=0.0, gamma_max=1.0, alpha=0.0, enable=True):
+        """Fokker-Planck energy coupling (Eq. Transpfp): the groups become the
+        Chebyshev nodes of gamma on [gamma_min, gamma_max]; enable=False turns it off."""
+        self._call(self.lib.sp6_set_energy_coupling, ctypes.c_int32(1 if enable else 0), ctypes.c_double(gamma_min),
+                   ctypes.c_double(gamma_max), ctypes.c_double(alpha))
+
     def set_inflow(self, g_in=None, g_out=None):
         s = self.plane_shape
         self._call(self.lib.sp6_set_inflow, _ptr(g_in, "g_in", s), _ptr(g_out, "g_out", s))
@@ -168,7 +174,7 @@ class Sp6Grid:
                    ctypes.c_int32(nsteps))
         return F
 
-    KERNEL_CLASSES = ("phi", "theta", "radial", "plane", "filter", "thetaphi")
+    KERNEL_CLASSES = ("phi", "theta", "radial", "plane", "filter", "thetaphi", "energy")
 
     def step_timed(self, F, dt, nsteps=1):
         """step() with per-kernel HIP-event timing; returns {class: (ms_total, launches)}."""

@@ -1,0 +1,162 @@
+"""Fokker-Planck energy coupling on the GPU (sp6_set_energy_coupling; Sect. 3.2,
+Eq. Transpfp) against the FP64 oracle (oracle/energy.py): right-hand sides and
+RK4 steps element by element at 1e-12 on every plane kernel (2 x 4, 16 x 32 and
+32 x 64 planes) with the isotropic and the Thomson phase function, the split
+step, the step without allocation, the refusals, and at full angular size a
+property that holds at any size: a homogeneous isotropic Bose distribution
+(Eq. Bose) is steady to the accuracy of the energy collocation."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import energy, grid as og, step
+from tests.gpu_util import need_gpu, maxrel, to_dev, to_host, oracle_grid, small, banner, stable_dt
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+GAMMA = (0.0, 1.0, 0.05)  # gamma_min, gamma_max, alpha
+THOMSON = (0.0, 0.75)
+
+SHAPES = {
+    "tiny": small(3, n_eps=4, n_r=5, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4),
+    "planes16": small(3, n_eps=6, n_r=5, n_theta=4, n_phi=8, n_Theta=16, n_Phi=32),
+    "planes32": small(3, n_eps=3, n_r=3, n_theta=2, n_phi=4, n_Theta=32, n_Phi=64),
+}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+    import paper_1104_5330_amd  # noqa: F401
+
+
+def setup(cfg, kernel, seed=0, energy_on=True):
+    from paper_1104_5330_amd import Sp6Grid
+    G = Sp6Grid.from_config(cfg, scattering=True)
+    if kernel is not None:
+        G.set_scattering_kernel(*kernel)
+    F = synth.fields.random_state(cfg, seed)
+    k, s, e = synth.fields.random_coeffs(cfg, seed + 1)
+    G.set_coefficients(to_dev(k), to_dev(s), to_dev(e))
+    if energy_on:
+        G.set_energy_coupling(*GAMMA)
+    p = step.Physics(k, s, e, bc=True, scattering=True, kernel=kernel, energy=GAMMA if energy_on else None)
+    return G, F, p
+
+
+@pytest.mark.parametrize("kernel", [None, THOMSON], ids=["isotropic", "thomson"])
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_rhs(name, kernel):
+    cfg = SHAPES[name]
+    G, F, p = setup(cfg, kernel, seed=3)
+    g = oracle_grid(cfg)
+    got = to_host(G.rhs(to_dev(F)))
+    want = step.rhs(F, g, p)
+    err = maxrel(got, want)
+    banner(f"energy rhs {name} {kernel}: max-rel {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_steps(name):
+    cfg = SHAPES[name]
+    G, F, p = setup(cfg, THOMSON, seed=5)
+    g = oracle_grid(cfg)
+    dt = 0.25 * stable_dt(cfg)
+    want = step.run(F, g, p, dt, 3)
+    Fd = to_dev(F)
+    G.step(Fd, dt, 3)
+    err = maxrel(to_host(Fd), want)
+    banner(f"energy steps {name}: max-rel {err:.2e}")
+    assert err <= TOL
+
+
+def test_split_step_and_noalloc():
+    cfg = SHAPES["planes16"]
+    G, F, p = setup(cfg, THOMSON, seed=7)
+    g = oracle_grid(cfg)
+    dt = 0.25 * stable_dt(cfg)
+    p.radial_implicit = True
+    want = step.run(F, g, p, dt, 2)
+    Fd = to_dev(F)
+    G.step_radial_implicit(Fd, dt, 2)
+    assert maxrel(to_host(Fd), want) <= TOL
+    A, B = to_dev(F), to_dev(F)
+    G.step(A, dt, 2)
+    G.step_noalloc(B, dt, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(A, B)
+
+
+def test_refusals_and_switching_off():
+    from paper_1104_5330_amd import Sp6Grid, _lib
+    cfg = SHAPES["tiny"]
+    G, F, _ = setup(cfg, None, seed=9, energy_on=False)
+    lib, h = G.lib, G._h
+    Fd = to_dev(F)
+    plain = G.rhs(Fd).clone()
+    call = lambda *a: lib.sp6_set_energy_coupling(h, ctypes.c_int32(1), *(ctypes.c_double(v) for v in a))
+    assert call(1.0, 1.0, 0.1) == _lib.SP6_ERR_ARG
+    assert call(-0.5, 1.0, 0.1) == _lib.SP6_ERR_ARG
+    assert call(0.0, 1.0, -0.1) == _lib.SP6_ERR_ARG
+    assert call(0.0, float("inf"), 0.1) == _lib.SP6_ERR_ARG
+    G.set_energy_coupling(*GAMMA)
+    on = G.rhs(Fd).clone()
+    assert not torch.equal(on, plain)
+    lam = to_dev(synth.fields.random_state(cfg, 10))
+    assert lib.sp6_adjoint_step(h, ctypes.c_void_p(Fd.data_ptr()), ctypes.c_double(cfg.dt),
+                                ctypes.c_void_p(lam.data_ptr()), None, None, None) == _lib.SP6_ERR_STATE
+    H = torch.zeros_like(Fd)
+    assert lib.sp6_step_ab2(h, ctypes.c_void_p(Fd.data_ptr()), ctypes.c_void_p(H.data_ptr()), ctypes.c_double(cfg.dt),
+                            ctypes.c_int32(1), ctypes.c_int32(1)) == _lib.SP6_ERR_STATE
+    G.set_energy_coupling(enable=False)
+    off = G.rhs(Fd)
+    torch.cuda.synchronize()
+    assert torch.equal(off, plain)
+    G.close()
+    # handles that cannot take it
+    for kw, code in ((dict(precision="mixed"), _lib.SP6_ERR_STATE), (dict(scattering=False), _lib.SP6_ERR_STATE)):
+        H2 = Sp6Grid.from_config(cfg, **kw)
+        st = H2.lib.sp6_set_energy_coupling(H2._h, ctypes.c_int32(1), ctypes.c_double(0.0), ctypes.c_double(1.0),
+                                            ctypes.c_double(0.1))
+        assert st == code, kw
+        H2.close()
+    one = Sp6Grid.from_config(small(3, n_eps=1, n_r=5, n_theta=2, n_phi=4, n_Theta=2, n_Phi=4))
+    st = one.lib.sp6_set_energy_coupling(one._h, ctypes.c_int32(1), ctypes.c_double(0.0), ctypes.c_double(1.0),
+                                         ctypes.c_double(0.1))
+    assert st == _lib.SP6_ERR_SHAPE
+    one.close()
+
+
+def test_bose_distribution_is_steady_full_angular_size():
+    """Workload 2's spatial and angular grid (33 x 16 x 32 x 16 x 32) with 32
+    energy nodes: a homogeneous isotropic Bose distribution, Thomson scattering,
+    no absorption or emission.  Streaming and scattering leave it unchanged and
+    the energy flux vanishes, so the right-hand side is zero up to the energy
+    collocation error (the oracle's own Bose test: 4e-11 of the drift term)."""
+    from paper_1104_5330_amd import Sp6Grid
+    n, (gmin, gmax, alpha, mu) = 32, (0.0, 2.0, 0.2, -1.0)
+    cfg = small(2, n_eps=n)
+    gam = energy.energy_nodes(n, gmin, gmax)
+    bose = 2.0 * gam * gam / np.expm1((gam - mu) / alpha)
+    D = og.cheb_diff_matrix(n, gmin, gmax)
+    scale = np.max(np.abs(D @ (gam * gam * bose)))
+    G = Sp6Grid.from_config(cfg, scattering=True)
+    G.set_scattering_kernel(*THOMSON)
+    shp = (cfg.n_eps, cfg.n_r, cfg.n_theta, cfg.n_phi)
+    z = torch.zeros(shp, dtype=torch.float64, device="cuda")
+    G.set_coefficients(z, z + 1.0, z)
+    G.set_energy_coupling(gmin, gmax, alpha)
+    F = torch.as_tensor(bose, device="cuda").view(-1, 1, 1, 1, 1, 1).expand(cfg.shape).contiguous()
+    G.set_inflow(F[:, 0].contiguous(), F[:, -1].contiguous())
+    r = G.rhs(F)
+    torch.cuda.synchronize()
+    rel = float(r.abs().max()) / scale
+    banner(f"Bose state on {cfg.shape}: max |rhs| / drift scale = {rel:.2e}")
+    assert rel <= 1e-9
+    G.close()
