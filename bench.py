@@ -54,7 +54,9 @@ METRIC = "6D grid-point updates/s per RK4 step (FP64 vs mixed vs adjoint), % HBM
 #              (acc's base y + (Y - y)/3 recovered, not read)
 #            stage 3 read Y, T, y, acc; write acc, Y'          48
 #            stage 4 read Y, T, acc; write y                   32   -> mean 36
-BYTES_FP64 = {"thetaphi": 16.0, "phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 36.0}
+# energy coupling (per stage): the moment pass reads the stage state once (8);
+# the pass over the groups moves 40 B per plane, negligible beside it
+BYTES_FP64 = {"thetaphi": 16.0, "phi": 16.0, "theta": 24.0, "radial": 24.0, "plane": 36.0, "energy": 8.0}
 # Mixed path (stage copy and T in FP32; stage 1 reads the FP64 state):
 #   thetaphi, phi : (8 + 4, then 3 x (4 + 4)) / 4                9
 #   theta  : (8 + 4 + 4, then 3 x 12) / 4                       13
@@ -73,7 +75,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", choices=["all", "large", "fp64", "mixed", "thomson", "shell", "ab2", "implicit", "adjoint"],
+    ap.add_argument("--form", choices=["all", "large", "fp64", "mixed", "thomson", "energy", "shell", "ab2", "implicit",
+                                       "adjoint"],
                     default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -112,7 +115,7 @@ def kernel_table(kt, P, bpp, total_ms):
     return out
 
 
-def run_steps(cfg, precision, scattering, steps, warmup, F0=None, kernel=None):
+def run_steps(cfg, precision, scattering, steps, warmup, F0=None, kernel=None, energy=None, coeffs=None):
     import torch
     import synth
     from paper_1104_5330_amd import Sp6Grid
@@ -120,11 +123,14 @@ def run_steps(cfg, precision, scattering, steps, warmup, F0=None, kernel=None):
     dev = torch.device("cuda", 0)
     if F0 is None:
         F0 = synth.fields.shell_state(cfg, device=dev)
-    coeffs = [torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)]
+    if coeffs is None:
+        coeffs = [torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)]
     G = Sp6Grid.from_config(cfg, precision=precision, bc=True, scattering=scattering)
     G.set_coefficients(*coeffs)
     if kernel is not None:
         G.set_scattering_kernel(*kernel)
+    if energy is not None:
+        G.set_energy_coupling(*energy)
     W = F0.clone()
     G.step(W, cfg.dt, warmup)
     del W
@@ -218,6 +224,38 @@ def form_thomson(args):
         "value": P * args.steps / (ms / 1e3), "unit": "grid-point updates/s", "ms_per_step": ms / args.steps,
         "steps": args.steps, "dtype": "f64",
         "isotropic_same_workload": P * args.steps / (ms_iso / 1e3),
+        "kernels": kernel_table(kt, P, BYTES_FP64, ms),
+    }
+
+
+def form_energy(args):
+    """FP64 step of Eq. (Transpfp) on the grid of the 8-group workloads: Thomson
+    scattering with n sigma_Th = 1, no absorption or emission (as the equation is
+    written), and the Fokker-Planck energy coupling, the 8 groups taken as the
+    Chebyshev nodes of gamma on [0, 0.1], alpha = 0.01; the initial state is the
+    shell state times a Bose spectrum (mu = -0.02) in gamma (synthetic
+    parameters; the paper gives no numerical case).  Per stage the coupling adds
+    a moment pass over the stage state and a pass over the groups of each
+    position."""
+    import synth
+    import torch
+    cfg = synth.config(3)
+    en, mu = (0.0, 0.1, 0.01), -0.02
+    dev = torch.device("cuda", 0)
+    F0 = synth.fields.bose_shell_state(cfg, en[0], en[1], en[2], mu, device=dev)
+    z = torch.zeros((cfg.n_eps, cfg.n_r, cfg.n_theta, cfg.n_phi), dtype=torch.float64, device=dev)
+    co = (z, z + 1.0, z)
+    _, _, ms, kt = run_steps(cfg, "fp64", True, args.steps, args.warmup, F0=F0, kernel=(0.0, 0.75), energy=en,
+                             coeffs=co)
+    _, _, ms_off, _ = run_steps(cfg, "fp64", True, args.steps, 0, F0=F0, kernel=(0.0, 0.75), coeffs=co)
+    P = cfg.points
+    return {
+        "workload": cfg.name, "grid": list(cfg.shape),
+        "physics": "Thomson scattering (n sigma_Th = 1) + Fokker-Planck energy coupling, no absorption or emission",
+        "gamma_range": [en[0], en[1]], "alpha": en[2], "initial_state": f"shell state x Bose spectrum, mu = {mu}",
+        "value": P * args.steps / (ms / 1e3), "unit": "grid-point updates/s", "ms_per_step": ms / args.steps,
+        "steps": args.steps, "dtype": "f64",
+        "without_coupling_ms_per_step": ms_off / args.steps,
         "kernels": kernel_table(kt, P, BYTES_FP64, ms),
     }
 
@@ -474,6 +512,8 @@ def main():
         forms["mixed"] = form_mixed(args)
     if args.form in ("all", "thomson"):
         forms["thomson"] = form_thomson(args)
+    if args.form in ("all", "energy"):
+        forms["energy"] = form_energy(args)
     if args.form in ("all", "shell"):
         forms["shell"] = form_shell(args)
     if args.form in ("all", "ab2"):

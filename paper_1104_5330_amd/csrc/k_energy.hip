@@ -15,10 +15,9 @@
 //
 // Two passes per right-hand side, ahead of the plane pass, which then takes
 // eta + sigma S as its emissivity:
-//   k_fp_moments: one workgroup per plane reduces the plane to (M0, Q): 20
-//     moments summed per thread from the coalesced plane, reduced over the
-//     wavefront and then over the wavefronts in a fixed order (8 bytes read per
-//     point, 16 written per plane);
+//   k_fp_moments: each plane reduced to (M0, Q): lane = column of the plane,
+//     20 moments summed over its rows, then reduced over the plane's lanes
+//     (8 bytes read per point, 16 written per plane);
 //   k_fp_source: one workgroup per position (r, theta, phi), thread k for group
 //     k: the two collocation products in gamma across the groups of that
 //     position, then eta_eff = eta + sigma S for each group's plane.
@@ -29,81 +28,124 @@ namespace {
 constexpr int FP_THREADS = 256;
 constexpr int FP_MAXG = 64;  // largest number of energy groups with the coupling on
 
+// contraction weight of moment k in Q = M0^2 - M1.M1 + M2:M2 - M3:.M3 (each
+// off-diagonal component of a symmetric tensor counts once per index order)
+SP6_DEV double q_weight(int k) {
+  if (k == 0) return 1.0;
+  if (k <= 3) return -1.0;
+  if (k <= 6) return 1.0;
+  if (k <= 9) return 2.0;
+  if (k <= 12) return -1.0;
+  if (k <= 18) return -3.0;
+  if (k == 19) return -6.0;
+  return 0.0;
+}
+
+// one step of the transposed reduction: a lane keeps the half of its C values
+// selected by bit O of its lane index and receives the partner's share of it
+template <int O, int C>
+SP6_DEV void tr_step(double (&v)[32], int lane) {
+  if constexpr (C == 1) {
+    v[0] += __shfl_xor(v[0], O, 64);
+  } else {
+    constexpr int H = C / 2;
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      const double send = up ? v[j] : v[H + j];
+      const double keep = up ? v[H + j] : v[j];
+      v[j] = keep + __shfl_xor(send, O, 64);
+    }
+  }
+}
+
+// Lanes take the columns (Phi nodes) of 64 / NP planes; each lane sums the 20
+// moments over the Theta rows of its column, then the lanes of a plane reduce
+// them.  For NP >= 32 the reduction is transposed: at each butterfly step a lane
+// keeps one half of its values and trades the other half with its partner, so
+// that after the steps lane l of the plane holds moment l (NP = 32) or l / 2
+// (NP = 64) summed over the plane (31 or 32 exchanges instead of 20 log2 NP);
+// Q is then a weighted sum of squares over those lanes.
+template <int NP>
 __global__ __launch_bounds__(FP_THREADS) void k_fp_moments(KDims d, KTab t, const double* __restrict__ Y,
                                                            double* __restrict__ mq) {
-  __shared__ double sW[32], sCT[32], sST[32], sCP[64], sSP[64];
-  __shared__ double sRed[FP_THREADS / 64][20];
+  __shared__ double sW[32], sCT[32], sST[32];
   const int tid = threadIdx.x;
   if (tid < d.n_Th) {
     sW[tid] = 4.0 * M_PI * t.wmean[tid];  // w_i (2 pi / n_Phi)
     sCT[tid] = t.cos_Th[tid];
     sST[tid] = t.sin_Th[tid];
   }
-  if (tid < d.n_Ph) {
-    sCP[tid] = t.cos_Ph[tid];
-    sSP[tid] = t.sin_Ph[tid];
-  }
   __syncthreads();
-  const int64_t pid = blockIdx.x;
-  const double* __restrict__ P = Y + pid * d.plane;
-  const int sh = __builtin_ctz(d.n_Ph), mk = d.n_Ph - 1;
-  // moments: 0; x y z; xx yy zz xy xz yz; xxx yyy zzz xxy xxz xyy yyz xzz yzz xyz
-  double m[20];
+  constexpr int PPW = 64 / NP;  // planes per wavefront
+  const int lane = tid & 63, nT = d.n_Th;
+  const int pl = lane / NP, m = lane % NP;  // plane within the group, column
+  const double cP = t.cos_Ph[m], sP = t.sin_Ph[m];
+  const int64_t ngroups = (d.nplanes + PPW - 1) / PPW;
+  const int64_t wstep = int64_t(gridDim.x) * (FP_THREADS / 64);
+  for (int64_t gi = int64_t(blockIdx.x) * (FP_THREADS / 64) + (tid >> 6); gi < ngroups; gi += wstep) {
+    const int64_t pid = gi * PPW + pl;
+    const bool ok = pid < d.nplanes;
+    double v[32];
 #pragma unroll
-  for (int k = 0; k < 20; ++k) m[k] = 0.0;
-  for (int p = tid; p < d.plane; p += FP_THREADS) {
-    const int i = p >> sh, j = p & mk;
-    const double f = sW[i] * P[p];
-    const double x = sCT[i], y = sST[i] * sCP[j], z = sST[i] * sSP[j];
-    const double fx = f * x, fy = f * y, fz = f * z;
-    m[0] += f;
-    m[1] += fx;
-    m[2] += fy;
-    m[3] += fz;
-    m[4] += fx * x;
-    m[5] += fy * y;
-    m[6] += fz * z;
-    m[7] += fx * y;
-    m[8] += fx * z;
-    m[9] += fy * z;
-    m[10] += fx * x * x;
-    m[11] += fy * y * y;
-    m[12] += fz * z * z;
-    m[13] += fx * x * y;
-    m[14] += fx * x * z;
-    m[15] += fx * y * y;
-    m[16] += fy * y * z;
-    m[17] += fx * z * z;
-    m[18] += fy * z * z;
-    m[19] += fx * y * z;
-  }
-#pragma unroll
-  for (int k = 0; k < 20; ++k) {
-    double v = m[k];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    if ((tid & 63) == 0) sRed[tid >> 6][k] = v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double M[20];
-#pragma unroll
-    for (int k = 0; k < 20; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int w = 0; w < FP_THREADS / 64; ++w) s += sRed[w][k];
-      M[k] = s;
+    for (int k = 0; k < 32; ++k) v[k] = 0.0;
+    if (ok) {
+      const double* __restrict__ col = Y + pid * d.plane + m;
+      for (int i = 0; i < nT; ++i) {
+        const double f = sW[i] * col[i * NP];
+        const double x = sCT[i], y = sST[i] * cP, z = sST[i] * sP;
+        const double fx = f * x, fy = f * y, fz = f * z;
+        v[0] += f;
+        v[1] += fx;
+        v[2] += fy;
+        v[3] += fz;
+        v[4] += fx * x;
+        v[5] += fy * y;
+        v[6] += fz * z;
+        v[7] += fx * y;
+        v[8] += fx * z;
+        v[9] += fy * z;
+        v[10] += fx * x * x;
+        v[11] += fy * y * y;
+        v[12] += fz * z * z;
+        v[13] += fx * x * y;
+        v[14] += fx * x * z;
+        v[15] += fx * y * y;
+        v[16] += fy * y * z;
+        v[17] += fx * z * z;
+        v[18] += fy * z * z;
+        v[19] += fx * y * z;
+      }
     }
-    // full contractions: each off-diagonal component of a symmetric tensor
-    // stands for as many entries as it has index permutations
-    const double m1 = M[1] * M[1] + M[2] * M[2] + M[3] * M[3];
-    const double m2 = M[4] * M[4] + M[5] * M[5] + M[6] * M[6] + 2.0 * (M[7] * M[7] + M[8] * M[8] + M[9] * M[9]);
-    const double m3 = M[10] * M[10] + M[11] * M[11] + M[12] * M[12] +
-                      3.0 * (M[13] * M[13] + M[14] * M[14] + M[15] * M[15] + M[16] * M[16] + M[17] * M[17] +
-                             M[18] * M[18]) +
-                      6.0 * M[19] * M[19];
-    mq[2 * pid] = M[0];
-    mq[2 * pid + 1] = M[0] * M[0] - m1 + m2 - m3;
+    double M0, Q = 0.0;
+    if constexpr (NP >= 32) {
+      if constexpr (NP == 64) tr_step<32, 32>(v, lane);
+      constexpr int C0 = NP == 64 ? 16 : 32;  // values held before the offset-16 step
+      tr_step<16, C0>(v, lane);
+      tr_step<8, C0 / 2>(v, lane);
+      tr_step<4, C0 / 4>(v, lane);
+      tr_step<2, C0 / 8>(v, lane);
+      tr_step<1, C0 / 16>(v, lane);
+      const int k = NP == 64 ? (lane >> 1) & 31 : lane & 31;
+      const bool own = NP == 32 || (lane & 1) == 0;  // one lane per moment
+      double q = own ? q_weight(k) * v[0] * v[0] : 0.0;
+#pragma unroll
+      for (int o = 1; o < NP; o <<= 1) q += __shfl_xor(q, o, 64);
+      Q = q;
+      M0 = v[0];  // the plane's first lane holds moment 0
+    } else {
+#pragma unroll
+      for (int k = 0; k < 20; ++k)
+#pragma unroll
+        for (int o = 1; o < NP; o <<= 1) v[k] += __shfl_xor(v[k], o, 64);
+      M0 = v[0];
+#pragma unroll
+      for (int k = 0; k < 20; ++k) Q += q_weight(k) * v[k] * v[k];
+    }
+    if (ok && m == 0) {
+      mq[2 * pid] = M0;
+      mq[2 * pid + 1] = Q;
+    }
   }
 }
 
@@ -145,8 +187,19 @@ __global__ __launch_bounds__(FP_MAXG) void k_fp_source(KDims d, const double* __
 hipError_t launch_fp_source(const KDims& d, const KTab& t, const double* Y, const double* D, const double* gam,
                             double alpha, double* mq, const double* eta, const double* sigma, double* eta_eff,
                             hipStream_t s) {
-  if (d.n_eps > FP_MAXG || d.n_Th > 32 || d.n_Ph > 64) return hipErrorInvalidValue;
-  k_fp_moments<<<unsigned(d.nplanes), FP_THREADS, 0, s>>>(d, t, Y, mq);
+  if (d.n_eps > FP_MAXG || d.n_Th > 32 || d.n_Ph > 64 || (d.n_Ph & (d.n_Ph - 1))) return hipErrorInvalidValue;
+  const int64_t ngroups = (d.nplanes + 64 / d.n_Ph - 1) / (64 / d.n_Ph);
+  int64_t blocks = (ngroups + FP_THREADS / 64 - 1) / (FP_THREADS / 64);
+  const int64_t cap = int64_t(d.ncu) * 8;
+  if (blocks > cap) blocks = cap;
+  switch (d.n_Ph) {
+    case 4: k_fp_moments<4><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
+    case 8: k_fp_moments<8><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
+    case 16: k_fp_moments<16><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
+    case 32: k_fp_moments<32><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
+    case 64: k_fp_moments<64><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
+    default: return hipErrorInvalidValue;
+  }
   const int64_t per = d.nplanes / d.n_eps;
   k_fp_source<<<unsigned(per), FP_MAXG, 0, s>>>(d, D, gam, alpha, mq, eta, sigma, eta_eff);
   return hipGetLastError();

@@ -199,6 +199,21 @@ def smooth_random_G(cfg, seed=0, kmax=10, device=None):
     return out if device is not None else out.numpy()
 
 
+def bose_shell_state(cfg, gamma_min, gamma_max, alpha, mu, seed=0, device=None):
+    """shell_state with its groups taken as the Chebyshev-Gauss-Lobatto energies
+    gamma_k of [gamma_min, gamma_max] (ascending) and scaled by the Bose spectrum
+    2 gamma^2 / (exp((gamma - mu) / alpha) - 1) there: an input for runs with the
+    energy coupling on."""
+    k = np.arange(cfg.n_eps)
+    gam = 0.5 * (gamma_min + gamma_max) - 0.5 * (gamma_max - gamma_min) * np.cos(np.pi * k / (cfg.n_eps - 1))
+    spec = 2.0 * gam * gam / np.expm1((gam - mu) / alpha)
+    F = shell_state(cfg, seed=seed, device=device)
+    if device is not None:
+        import torch
+        return F * torch.as_tensor(spec, dtype=torch.float64, device=F.device).view(-1, 1, 1, 1, 1, 1)
+    return F * spec.reshape(-1, 1, 1, 1, 1, 1)
+
+
 def shell_state(cfg, seed=0, device=None):
     """(r - r_in)(r_out - r) [1 + 0.5 G] for every energy group; zero on both
     radial boundaries, so it satisfies zero inflow."""
