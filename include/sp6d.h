@@ -142,8 +142,8 @@ sp6_status sp6_set_scattering_kernel(sp6_grid grid, double c1, double c2);
  * (Transpfp).  The sign is the one for which the energy diffusion runs forward
  * and the Bose distribution of Eq. (Bose) is steady; the printed Eq. (Kompa) has
  * the opposite overall sign.  The source is added to eta, so it is zero at the
- * inflow nodes with the rest of the right-hand side.  Nonlinear in F: while it is
- * on, sp6_adjoint_step(_stages) and sp6_step_ab2 return SP6_ERR_STATE.
+ * inflow nodes with the rest of the right-hand side; sp6_step_ab2 takes it too.
+ * Nonlinear in F: while it is on, sp6_adjoint_step(_stages) return SP6_ERR_STATE.
  * enable = 0 turns it off (the other arguments are ignored).  Needs an FP64
  * handle created with scattering = 1 (SP6_ERR_STATE), 2 <= n_eps <= 64
  * (SP6_ERR_SHAPE), 0 <= gamma_min < gamma_max and alpha >= 0, finite

@@ -852,7 +852,6 @@ sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nst
   if (nsteps < 0) return fail(SP6_ERR_ARG, "nsteps must be >= 0");
   if (start != 0 && start != 1) return fail(SP6_ERR_ARG, "start must be 0 or 1");
   if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "sp6_step_ab2 needs an FP64 handle");
-  if (g->fp_on) return fail(SP6_ERR_STATE, "sp6_step_ab2 does not take the energy coupling (sp6_set_energy_coupling)");
   if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
   if (sp6_status s = check_state_io(g, F, "F", H, "H")) return s;
   if (nsteps == 0) return SP6_OK;
@@ -879,7 +878,9 @@ sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nst
       a.accsrc = H, a.cb = dt;
       a.ysrc = H, a.cn = 1.5 * dt;
     }
-    HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
+    KCoef c = g->c;
+    HIP_TRY(rhs_coefs(g, F, &c), "energy coupling");
+    HIP_TRY(launch_plane(next_pass(g), g->t, c, a, g->stream), "plane pass");
     if (g->desc.filter) {
       // H = F - (dt/2) k with k zero at the inflow nodes: H holds the inflow values too
       HIP_TRY(filter_step(g, F), "filter");
