@@ -131,7 +131,8 @@ sp6_status sp6_set_scattering_kernel(sp6_grid grid, double c1, double c2);
  * energy groups are taken as the Chebyshev-Gauss-Lobatto nodes gamma_k of
  * [gamma_min, gamma_max] (ascending, k = 0 first), and every right-hand side of
  * sp6_rhs and the RK4 steps (sp6_step, _stages, _noalloc, _timed,
- * _radial_implicit) gains, per (eps, r, theta, phi) plane, the isotropic source
+ * _radial_implicit; FP64 and mixed) gains, per (eps, r, theta, phi) plane, the
+ * isotropic source
  *   sigma S,  S = (1/4pi) d/dgamma [alpha gamma^2 dM0/dgamma + (gamma^2 - 2 alpha gamma) M0]
  *               + 3/(128 pi^2) dQ/dgamma,
  *   M0 = int F dw,  Q = int int (1 - mu + mu^2 - mu^3) F(w') F(w'') dw' dw'',
@@ -143,11 +144,12 @@ sp6_status sp6_set_scattering_kernel(sp6_grid grid, double c1, double c2);
  * and the Bose distribution of Eq. (Bose) is steady; the printed Eq. (Kompa) has
  * the opposite overall sign.  The source is added to eta, so it is zero at the
  * inflow nodes with the rest of the right-hand side; sp6_step_ab2 takes it too.
- * Nonlinear in F: while it is on, sp6_adjoint_step(_stages) return SP6_ERR_STATE.
- * enable = 0 turns it off (the other arguments are ignored).  Needs an FP64
- * handle created with scattering = 1 (SP6_ERR_STATE), 2 <= n_eps <= 64
- * (SP6_ERR_SHAPE), 0 <= gamma_min < gamma_max and alpha >= 0, finite
- * (SP6_ERR_ARG).  Allocates three per-plane device arrays on first use. */
+ * On the mixed path the moment pass reads the FP32 stage copy; the source is
+ * formed in FP64.  Nonlinear in F: while it is on, sp6_adjoint_step(_stages)
+ * return SP6_ERR_STATE.  enable = 0 turns it off (the other arguments are
+ * ignored).  Needs a handle created with scattering = 1 (SP6_ERR_STATE),
+ * 2 <= n_eps <= 64 (SP6_ERR_SHAPE), 0 <= gamma_min < gamma_max and alpha >= 0,
+ * finite (SP6_ERR_ARG).  Allocates three per-plane device arrays on first use. */
 sp6_status sp6_set_energy_coupling(sp6_grid grid, int32_t enable, double gamma_min, double gamma_max,
                                    double alpha);
 

@@ -304,10 +304,10 @@ hipError_t ensure_f32(sp6_grid g, float** p) {
 
 // The coefficients of a right-hand side of the stage input Y: the handle's, or
 // with the energy coupling on, with eta + sigma S(Y) as the emissivity
-hipError_t rhs_coefs(sp6_grid g, const double* Y, KCoef* c, Timer* tm = nullptr) {
+hipError_t rhs_coefs(sp6_grid g, const void* Y, bool y_f32, KCoef* c, Timer* tm = nullptr) {
   *c = g->c;
   if (!g->fp_on) return hipSuccess;
-  hipError_t e = launch_fp_source(g->d, g->t, Y, g->fp_D, g->fp_gam, g->fp_alpha, g->fp_mq, g->eta, g->sigma,
+  hipError_t e = launch_fp_source(g->d, g->t, Y, y_f32, g->fp_D, g->fp_gam, g->fp_alpha, g->fp_mq, g->eta, g->sigma,
                                   g->fp_eta, g->stream);
   if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_ENERGY);
   c->eta = g->fp_eta;
@@ -334,7 +334,7 @@ sp6_status fp64_rhs_like(sp6_grid g, const double* F, double* out, int mode, uin
   a.out = out;
   a.terms = terms;
   KCoef c = g->c;
-  if (mode == PM_RHS) HIP_TRY(rhs_coefs(g, F, &c), "energy coupling");
+  if (mode == PM_RHS) HIP_TRY(rhs_coefs(g, F, false, &c), "energy coupling");
   HIP_TRY(launch_plane(next_pass(g), g->t, c, a, g->stream), "plane pass");
   return SP6_OK;
 }
@@ -563,7 +563,6 @@ sp6_status sp6_set_energy_coupling(sp6_grid g, int32_t enable, double gamma_min,
     g->fp_on = false;
     return SP6_OK;
   }
-  if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "the energy coupling needs an FP64 handle");
   if (!g->desc.scattering) return fail(SP6_ERR_STATE, "the energy coupling needs scattering = 1 (its source scales with sigma)");
   const int n = g->desc.n_eps;
   if (n < 2 || n > 64) return fail(SP6_ERR_SHAPE, "the energy coupling needs 2 <= n_eps <= 64 (Chebyshev nodes of gamma)");
@@ -785,7 +784,7 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
           break;
       }
       KCoef c = g->c;
-      if (!mixed) HIP_TRY(rhs_coefs(g, static_cast<const double*>(a.Yin), &c, tm), "energy coupling");
+      HIP_TRY(rhs_coefs(g, a.Yin, mixed && a.yin_f32, &c, tm), "energy coupling");
       HIP_TRY(launch_plane(next_pass(g), g->t, c, a, g->stream), "plane pass");
       if (tm) HIP_TRY(tm->mark(g->stream, KC_PLANE), "event");
     }
@@ -879,7 +878,7 @@ sp6_status sp6_step_ab2(sp6_grid g, double* F, double* H, double dt, int32_t nst
       a.ysrc = H, a.cn = 1.5 * dt;
     }
     KCoef c = g->c;
-    HIP_TRY(rhs_coefs(g, F, &c), "energy coupling");
+    HIP_TRY(rhs_coefs(g, F, false, &c), "energy coupling");
     HIP_TRY(launch_plane(next_pass(g), g->t, c, a, g->stream), "plane pass");
     if (g->desc.filter) {
       // H = F - (dt/2) k with k zero at the inflow nodes: H holds the inflow values too

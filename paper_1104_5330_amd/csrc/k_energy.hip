@@ -14,7 +14,8 @@
 // induced term of Eq. Transpfp the opposite sign of that term).
 //
 // Two passes per right-hand side, ahead of the plane pass, which then takes
-// eta + sigma S as its emissivity:
+// eta + sigma S as its emissivity (the moment pass reads the FP64 state or the
+// mixed path's FP32 stage copy; everything after it is FP64):
 //   k_fp_moments: each plane reduced to (M0, Q): lane = column of the plane,
 //     20 moments summed over its rows, then reduced over the plane's lanes
 //     (8 bytes read per point, 16 written per plane);
@@ -66,8 +67,8 @@ SP6_DEV void tr_step(double (&v)[32], int lane) {
 // that after the steps lane l of the plane holds moment l (NP = 32) or l / 2
 // (NP = 64) summed over the plane (31 or 32 exchanges instead of 20 log2 NP);
 // Q is then a weighted sum of squares over those lanes.
-template <int NP>
-__global__ __launch_bounds__(FP_THREADS) void k_fp_moments(KDims d, KTab t, const double* __restrict__ Y,
+template <int NP, typename TI>
+__global__ __launch_bounds__(FP_THREADS) void k_fp_moments(KDims d, KTab t, const TI* __restrict__ Y,
                                                            double* __restrict__ mq) {
   __shared__ double sW[32], sCT[32], sST[32];
   const int tid = threadIdx.x;
@@ -90,9 +91,9 @@ __global__ __launch_bounds__(FP_THREADS) void k_fp_moments(KDims d, KTab t, cons
 #pragma unroll
     for (int k = 0; k < 32; ++k) v[k] = 0.0;
     if (ok) {
-      const double* __restrict__ col = Y + pid * d.plane + m;
+      const TI* __restrict__ col = Y + pid * d.plane + m;
       for (int i = 0; i < nT; ++i) {
-        const double f = sW[i] * col[i * NP];
+        const double f = sW[i] * double(col[i * NP]);
         const double x = sCT[i], y = sST[i] * cP, z = sST[i] * sP;
         const double fx = f * x, fy = f * y, fz = f * z;
         v[0] += f;
@@ -184,22 +185,29 @@ __global__ __launch_bounds__(FP_MAXG) void k_fp_source(KDims d, const double* __
 
 }  // namespace
 
-hipError_t launch_fp_source(const KDims& d, const KTab& t, const double* Y, const double* D, const double* gam,
-                            double alpha, double* mq, const double* eta, const double* sigma, double* eta_eff,
-                            hipStream_t s) {
+hipError_t launch_fp_source(const KDims& d, const KTab& t, const void* Y, bool y_f32, const double* D,
+                            const double* gam, double alpha, double* mq, const double* eta, const double* sigma,
+                            double* eta_eff, hipStream_t s) {
   if (d.n_eps > FP_MAXG || d.n_Th > 32 || d.n_Ph > 64 || (d.n_Ph & (d.n_Ph - 1))) return hipErrorInvalidValue;
   const int64_t ngroups = (d.nplanes + 64 / d.n_Ph - 1) / (64 / d.n_Ph);
   int64_t blocks = (ngroups + FP_THREADS / 64 - 1) / (FP_THREADS / 64);
   const int64_t cap = int64_t(d.ncu) * 8;
   if (blocks > cap) blocks = cap;
+  const unsigned nb = unsigned(blocks);
+  const double* Yd = static_cast<const double*>(Y);
+  const float* Yf = static_cast<const float*>(Y);
+#define FP_CASE(N)                                                    \
+  case N:                                                             \
+    if (y_f32)                                                        \
+      k_fp_moments<N, float><<<nb, FP_THREADS, 0, s>>>(d, t, Yf, mq);  \
+    else                                                              \
+      k_fp_moments<N, double><<<nb, FP_THREADS, 0, s>>>(d, t, Yd, mq); \
+    break;
   switch (d.n_Ph) {
-    case 4: k_fp_moments<4><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
-    case 8: k_fp_moments<8><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
-    case 16: k_fp_moments<16><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
-    case 32: k_fp_moments<32><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
-    case 64: k_fp_moments<64><<<unsigned(blocks), FP_THREADS, 0, s>>>(d, t, Y, mq); break;
+    FP_CASE(4) FP_CASE(8) FP_CASE(16) FP_CASE(32) FP_CASE(64)
     default: return hipErrorInvalidValue;
   }
+#undef FP_CASE
   const int64_t per = d.nplanes / d.n_eps;
   k_fp_source<<<unsigned(per), FP_MAXG, 0, s>>>(d, D, gam, alpha, mq, eta, sigma, eta_eff);
   return hipGetLastError();

@@ -157,11 +157,12 @@ hipError_t launch_plane_adj(const KDims& d, const KTab& t, const KCoef& c, const
 hipError_t launch_plane_LT(const KDims& d, const KTab& t, const double* G, const double* T,
                            double* out, hipStream_t s);
 
-// Fokker-Planck energy coupling: (M0, Q) of every plane of Y into mq, then
-// eta_eff = eta + sigma S per plane (D: energy-node derivative, gam: nodes)
-hipError_t launch_fp_source(const KDims& d, const KTab& t, const double* Y, const double* D, const double* gam,
-                            double alpha, double* mq, const double* eta, const double* sigma, double* eta_eff,
-                            hipStream_t s);
+// Fokker-Planck energy coupling: (M0, Q) of every plane of Y (FP64, or FP32 with
+// y_f32) into mq, then eta_eff = eta + sigma S per plane (D: energy-node
+// derivative, gam: nodes)
+hipError_t launch_fp_source(const KDims& d, const KTab& t, const void* Y, bool y_f32, const double* D,
+                            const double* gam, double alpha, double* mq, const double* eta, const double* sigma,
+                            double* eta_eff, hipStream_t s);
 
 // filter, projection, diagnostics
 // the angular line filters, then (radial = 1) the radial filter or (radial = 2)
