@@ -14,7 +14,10 @@ k_s = rhs(Y_s), the exact transpose of the step is (lam = dLoss/dy1):
     dLoss/dy = lam + sum_s A^T kb_s
 
 and the coefficient gradients are sum_s (d rhs(Y_s) / d coeff)^T kb_s, which need
-the stage inputs Y_s (recomputed from y).  With the filter on, lam is first
+the stage inputs Y_s (recomputed from y).  With the energy coupling on the
+right-hand side is no longer affine: A^T is then the transpose of its Jacobian
+at each stage input, A^T + (M sigma S'(Y_s))^T (energy.fp_rhs_T), and sigma's
+gradient gains S(Y_s) summed against M kb_s.  With the filter on, lam is first
 set to zero at the inflow nodes (when the inflow conditions are on: the step
 re-imposes the inflow values after the filter) and mapped by the filter's
 transpose (the angular line filters are symmetric, the radial one is not).
@@ -22,7 +25,7 @@ transpose (the angular line filters are symmetric, the radial one is not).
 
 import numpy as np
 
-from . import ops, step, diagnostics
+from . import energy, ops, step, diagnostics
 
 
 def adjoint_step(y, lam, g, p, dt):
@@ -41,18 +44,23 @@ def adjoint_step(y, lam, g, p, dt):
             lam = lam * ops.inflow_mask(g)
         lam = ops.apply_filter_T(lam, g, radial=p.filt_r)
     (Y1, Y2, Y3, Y4), _ = step.rk4_stages(y, g, p, dt)
+    s_eff = p.sigma if p.scattering else np.zeros_like(np.asarray(p.sigma, np.float64))
 
-    def AT(x):
-        return ops.rhs_linear_T(x, g, p.kappa, p.sigma, bc=p.bc, scattering=p.scattering, kernel=p.kernel)
+    def AT(x, Ys):
+        # the transpose of the right-hand side's Jacobian at the stage input Ys
+        out = ops.rhs_linear_T(x, g, p.kappa, p.sigma, bc=p.bc, scattering=p.scattering, kernel=p.kernel)
+        if p.energy is not None:
+            out = out + energy.fp_rhs_T(Ys, x, g, s_eff, *p.energy, bc=p.bc)
+        return out
 
     kb4 = (dt / 6.0) * lam
-    a4 = AT(kb4)
+    a4 = AT(kb4, Y4)
     kb3 = (dt / 3.0) * lam + dt * a4
-    a3 = AT(kb3)
+    a3 = AT(kb3, Y3)
     kb2 = (dt / 3.0) * lam + 0.5 * dt * a3
-    a2 = AT(kb2)
+    a2 = AT(kb2, Y2)
     kb1 = (dt / 6.0) * lam + 0.5 * dt * a2
-    a1 = AT(kb1)
+    a1 = AT(kb1, Y1)
     lam_prev = lam + a1 + a2 + a3 + a4
 
     M = ops.inflow_mask(g) if p.bc else 1.0
@@ -65,6 +73,9 @@ def adjoint_step(y, lam, g, p, dt):
         ge += np.sum(mk, axis=(4, 5))
         if p.scattering:
             gs += np.sum(mk * (ops.scatter_in(Ys, g, p.kernel) - Ys), axis=(4, 5))
+            if p.energy is not None:
+                # the coupling's source is sigma S(Ys)
+                gs += np.sum(mk, axis=(4, 5)) * energy.fp_source(Ys, g, np.ones(gs.shape), *p.energy)
     return lam_prev, gk, ge, gs
 
 

@@ -92,6 +92,38 @@ def fp_source(F, g, sigma, gamma_min, gamma_max, alpha):
     return np.asarray(sigma, np.float64).reshape(S.shape) * S
 
 
+def fp_rhs_T(Y, X, g, sigma, gamma_min, gamma_max, alpha, bc=True):
+    """Transpose of the linearisation at Y of the coupling's part of the
+    right-hand side, F -> M sigma S(F) (broadcast over each plane, M the inflow
+    mask), applied to X (rank 6):
+
+        u  = sigma sum_w (M X)                    per plane
+        a0 = L1^T u,  aQ = 3/(128 pi^2) D^T u     along gamma, with
+        L1 = (1/4pi) D [diag(alpha gamma^2) D + diag(gamma^2 - 2 alpha gamma)]
+        A0 = a0 + 2 aQ M0,  A1 = -2 aQ M1,  A2 = 2 aQ M2,  A3 = -2 aQ M3
+        result(w) = wq(w) [A0 + A1.w + A2:ww + A3:.www]
+
+    (dQ = 2 (M0 dM0 - M1.dM1 + M2:dM2 - M3:.dM3); Mk the moments of Y; wq the
+    plane quadrature weight of the direction)."""
+    Xm = X * ops.inflow_mask(g) if bc else X
+    u = np.asarray(sigma, np.float64).reshape(Xm.shape[:4]) * Xm.sum(axis=(4, 5))
+    gam = energy_nodes(g.n_eps, gamma_min, gamma_max)
+    D = _grid.cheb_diff_matrix(g.n_eps, gamma_min, gamma_max)
+    L1 = D @ (np.diag(alpha * gam * gam) @ D + np.diag(gam * gam - 2.0 * alpha * gam)) / (4.0 * np.pi)
+    a0 = np.tensordot(L1.T, u, axes=(1, 0))
+    aQ = (3.0 / (128.0 * np.pi ** 2)) * np.tensordot(D.T, u, axes=(1, 0))
+    M0, M1, M2, M3 = moments(Y, g)
+    A0 = a0 + 2.0 * aQ * M0
+    A1 = -2.0 * aQ[..., None] * M1
+    A2 = 2.0 * aQ[..., None, None] * M2
+    A3 = -2.0 * aQ[..., None, None, None] * M3
+    om = ops.plane_directions(g).reshape(g.n_Theta, g.n_Phi, 3)
+    poly = (A0[..., None, None] + np.einsum("...a,ija->...ij", A1, om)
+            + np.einsum("...ab,ija,ijb->...ij", A2, om, om)
+            + np.einsum("...abc,ija,ijb,ijc->...ij", A3, om, om, om))
+    return poly * _quadrature(g)
+
+
 def kompaneets_flux(F, gam, dF, alpha):
     """The flux of Eq. (Kompa) for an isotropic, homogeneous F(gamma) given with
     its derivative dF: alpha gamma^2 F' + (gamma^2 - 2 alpha gamma) F + F^2/2."""

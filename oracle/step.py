@@ -61,12 +61,14 @@ def filter_step(y, g, p):
 
 
 def rhs(F, g, p):
-    eta = p.eta
+    out = ops.rhs(F, g, p.kappa, p.sigma, p.eta, bc=p.bc, scattering=p.scattering, kernel=p.kernel,
+                  radial=not p.radial_implicit)
     if p.energy is not None:
+        # the coupling's isotropic source sigma S(F), zero at the inflow nodes
         s = p.sigma if p.scattering else np.zeros_like(np.asarray(p.sigma, np.float64))
-        eta = np.asarray(p.eta, np.float64) + energy.fp_source(F, g, s, *p.energy)
-    return ops.rhs(F, g, p.kappa, p.sigma, eta, bc=p.bc, scattering=p.scattering, kernel=p.kernel,
-                   radial=not p.radial_implicit)
+        src = energy.fp_source(F, g, s, *p.energy)[..., None, None]
+        out = out + (src * ops.inflow_mask(g) if p.bc else src)
+    return out
 
 
 def rk4_stages(y, g, p, dt):

@@ -147,3 +147,54 @@ def test_rhs_adds_the_source_to_eta():
     src = energy.fp_source(F, g, s, 0.1, 1.1, 0.05)
     want = step.rhs(F, g, p0) + ops.expand_coeff(src, g) * ops.inflow_mask(g)
     assert np.max(np.abs(step.rhs(F, g, p1) - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def _coupled_case(seed, kernel=(0.0, 0.75)):
+    from oracle import step
+    g = _grid(5)
+    rng = np.random.default_rng(seed)
+    shp6 = (g.n_eps, g.n_r, g.n_theta, g.n_phi, g.n_Theta, g.n_Phi)
+    Y = 0.3 * rng.normal(size=shp6)
+    k, s, e = (rng.uniform(0.1, 1.0, shp6[:4]) for _ in range(3))
+    p = step.Physics(k, s, e, kernel=kernel, energy=(0.1, 1.1, 0.05))
+    return g, rng, shp6, Y, p
+
+
+@pytest.mark.parametrize("kernel", [None, (0.0, 0.75)], ids=["isotropic", "thomson"])
+def test_jacobian_transpose_by_complex_step(kernel):
+    """<X, J(Y) d> with J d = Im rhs(Y + i h d) / h (exact: the right-hand side is
+    analytic in F) equals <J(Y)^T X, d> from the linear transpose plus
+    fp_rhs_T."""
+    from oracle import step
+    g, rng, shp6, Y, p = _coupled_case(4, kernel)
+    d, X = rng.normal(size=shp6), rng.normal(size=shp6)
+    h = 1e-30
+    Jd = np.imag(step.rhs(Y + 1j * h * d, g, p)) / h
+    JT = ops.rhs_linear_T(X, g, p.kappa, p.sigma, kernel=p.kernel) + energy.fp_rhs_T(Y, X, g, p.sigma, *p.energy)
+    lhs, rhs = np.sum(X * Jd), np.sum(JT * d)
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), np.sum(np.abs(X * Jd))), (lhs, rhs)
+
+
+def test_adjoint_step_by_complex_step_and_differences():
+    """The adjoint RK4 step with the coupling: dLoss/dy against the complex-step
+    derivative of the step, and the sigma, kappa and eta gradients against central
+    differences (the coefficient fields enter through real-valued helpers)."""
+    from oracle import adjoint, step
+    g, rng, shp6, y, p = _coupled_case(5)
+    dt = 0.02
+    lam = rng.normal(size=shp6)
+    lam_prev, gk, ge, gs = adjoint.adjoint_step(y, lam, g, p, dt)
+    d = rng.normal(size=shp6)
+    h = 1e-30
+    dir_y = np.sum(lam * np.imag(step.rk4_step(y + 1j * h * d, g, p, dt))) / h
+    assert abs(dir_y - np.sum(lam_prev * d)) <= 1e-11 * np.sum(np.abs(lam_prev * d))
+    import dataclasses
+    for name, grad in (("sigma", gs), ("kappa", gk), ("eta", ge)):
+        dc = rng.normal(size=shp6[:4])
+        eps = 1e-6
+
+        def J(sign):
+            q = dataclasses.replace(p, **{name: getattr(p, name) + sign * eps * dc})
+            return np.sum(lam * step.rk4_step(y, g, q, dt))
+        fd = (J(1.0) - J(-1.0)) / (2.0 * eps)
+        assert abs(fd - np.sum(grad * dc)) <= 1e-6 * max(abs(fd), 1e-12), (name, fd, np.sum(grad * dc))
