@@ -83,6 +83,8 @@ struct sp6_grid_s {
   double* fp_gam = nullptr;
   double* fp_mq = nullptr;
   double* fp_eta = nullptr;
+  double* fp_mom = nullptr;  // adjoint: 20 moments and the masked sum per plane
+  double* fp_C = nullptr;    // adjoint: 20 direction-polynomial coefficients per plane
   std::vector<double> fp_host;  // host copy of D and the nodes (source of the uploads)
 
   hipError_t alloc(void** p, size_t n) {
@@ -917,7 +919,6 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
                         double* ge, double* gs) {
   if (sp6_status s = check_grid(g)) return s;
   if (g->desc.precision != SP6_FP64) return fail(SP6_ERR_STATE, "adjoint_step is FP64-only");
-  if (g->fp_on) return fail(SP6_ERR_STATE, "adjoint_step is not defined with the energy coupling (nonlinear)");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(SP6_ERR_ARG, "dt must be finite and > 0");
   if (!g->coeffs_set) return fail(SP6_ERR_STATE, "coefficients not set (call sp6_set_coefficients)");
   if (sp6_status s = check_state_io(g, Fn, "F_n", lam, "lam")) return s;
@@ -951,6 +952,10 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
   }
   HIP_TRY(ensure(g, &g->KB, B), "allocate scratch");
   HIP_TRY(ensure(g, &g->LACC, B), "allocate scratch");
+  if (g->fp_on) {
+    HIP_TRY(ensure(g, &g->fp_mom, 21 * size_t(g->d.nplanes) * sizeof(double)), "allocate scratch");
+    HIP_TRY(ensure(g, &g->fp_C, 20 * size_t(g->d.nplanes) * sizeof(double)), "allocate scratch");
+  }
   const KDims& d = g->d;
   if (g->desc.filter) HIP_TRY(filter_step_T(g, lam), "transposed filter of lam");
   double* Ys[5] = {nullptr, const_cast<double*>(Fn), g->Y2, g->Y3, g->Y4};
@@ -969,7 +974,9 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
     a.ysrc = (s == 1) ? nullptr : Fn;
     a.ynext = Ys[s + 1];
     a.cn = cn[s];
-    HIP_TRY(launch_plane(next_pass(g), g->t, g->c, a, g->stream), "plane pass");
+    KCoef c = g->c;
+    HIP_TRY(rhs_coefs(g, Ys[s], false, &c), "energy coupling");
+    HIP_TRY(launch_plane(next_pass(g), g->t, c, a, g->stream), "plane pass");
   }
   // transposed stages 4, 3, 2, 1
   for (int s = 4; s >= 1; --s) {
@@ -1000,7 +1007,16 @@ sp6_status adjoint_core(sp6_grid g, const double* Fn, const double* Ystages, dou
         a.lam = nullptr, a.laccsrc = g->LACC, a.laccdst = lam, a.kbnext = nullptr;
         break;
     }
+    // energy coupling: the transpose of its linearisation at Y_s, formed from x
+    // before the plane pass overwrites it (x and kbnext share KB), added after
+    // it to the two outputs, which are linear in the stage's transposed result
+    if (g->fp_on)
+      HIP_TRY(launch_fp_adj(d, g->t, Ys[s], x, xs, g->fp_D, g->fp_gam, g->fp_alpha, g->fp_mom, g->sigma, g->fp_C, gs,
+                            g->stream),
+              "energy coupling (adjoint)");
     HIP_TRY(launch_plane_adj(d, g->t, g->c, a, g->stream), "transposed plane pass");
+    if (g->fp_on)
+      HIP_TRY(launch_fp_adj_apply(d, g->t, g->fp_C, a.laccdst, a.kbnext, a.kb, g->stream), "energy coupling (adjoint)");
   }
   return SP6_OK;
 }

@@ -164,6 +164,16 @@ hipError_t launch_fp_source(const KDims& d, const KTab& t, const void* Y, bool y
                             const double* gam, double alpha, double* mq, const double* eta, const double* sigma,
                             double* eta_eff, hipStream_t s);
 
+// its adjoint: per plane the moments of the stage input Y and the masked sum
+// of X = xs x (mom), then the direction-polynomial coefficients C per plane and
+// sigma's gradient (gs, may be null); then lacc += p, kbnext += kb p with
+// p(w) = wq(w) sum_k C_k phi_k(w) (kbnext may be null)
+hipError_t launch_fp_adj(const KDims& d, const KTab& t, const double* Y, const double* X, double xs, const double* D,
+                         const double* gam, double alpha, double* mom, const double* sigma, double* C, double* gs,
+                         hipStream_t s);
+hipError_t launch_fp_adj_apply(const KDims& d, const KTab& t, const double* C, double* lacc, double* kbnext, double kb,
+                               hipStream_t s);
+
 // filter, projection, diagnostics
 // the angular line filters, then (radial = 1) the radial filter or (radial = 2)
 // its transpose, in place

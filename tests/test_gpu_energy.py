@@ -2,8 +2,8 @@
 Eq. Transpfp) against the FP64 oracle (oracle/energy.py): right-hand sides and
 RK4 steps element by element at 1e-12 on every plane kernel (2 x 4, 16 x 32 and
 32 x 64 planes) with the isotropic and the Thomson phase function, the split
-step, Adams-Bashforth, the step without allocation, the mixed path (at its
-stated bounds), the refusals, and at full
+step, Adams-Bashforth, the step without allocation, the adjoint step and its
+gradients, the mixed path (at its stated bounds), the refusals, and at full
 angular size a property that holds at any size: a homogeneous isotropic Bose
 distribution (Eq. Bose) is steady to the accuracy of the energy collocation."""
 
@@ -133,6 +133,34 @@ def test_mixed_path():
     G.close()
 
 
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_adjoint_step(name):
+    """The adjoint RK4 step with the coupling (the transpose of the step's
+    linearisation at its stage inputs) and the kappa, eta, sigma gradients against
+    the oracle, with the stage inputs recomputed and with them stored."""
+    from oracle import adjoint
+    cfg = SHAPES[name]
+    G, F, p = setup(cfg, THOMSON, seed=13)
+    g = oracle_grid(cfg)
+    dt = 0.25 * stable_dt(cfg)
+    lam = synth.fields.random_state(cfg, 14)
+    lam_prev, gk, ge, gs = adjoint.adjoint_step(F, lam, g, p, dt)
+    z = torch.zeros(cfg.shape[:4], dtype=torch.float64, device="cuda")
+    for stored in (False, True):
+        lam_d, gkd, ged, gsd = to_dev(lam), z.clone(), z.clone(), z.clone()
+        if stored:
+            Ys = torch.empty((3,) + cfg.shape, dtype=torch.float64, device="cuda")
+            G.step_stages(to_dev(F), dt, Ys)
+            G.adjoint_step_stages(to_dev(F), Ys, dt, lam_d, gkd, ged, gsd)
+        else:
+            G.adjoint_step(to_dev(F), dt, lam_d, gkd, ged, gsd)
+        errs = [maxrel(to_host(lam_d), lam_prev), maxrel(to_host(gkd), gk), maxrel(to_host(ged), ge),
+                maxrel(to_host(gsd), gs)]
+        banner(f"energy adjoint {name} stored={stored}: lam {errs[0]:.2e} gk {errs[1]:.2e} ge {errs[2]:.2e} "
+               f"gs {errs[3]:.2e}")
+        assert errs[0] <= TOL and max(errs[1:]) <= 1e-11
+
+
 def test_refusals_and_switching_off():
     from paper_1104_5330_amd import Sp6Grid, _lib
     cfg = SHAPES["tiny"]
@@ -148,9 +176,6 @@ def test_refusals_and_switching_off():
     G.set_energy_coupling(*GAMMA)
     on = G.rhs(Fd).clone()
     assert not torch.equal(on, plain)
-    lam = to_dev(synth.fields.random_state(cfg, 10))
-    assert lib.sp6_adjoint_step(h, ctypes.c_void_p(Fd.data_ptr()), ctypes.c_double(cfg.dt),
-                                ctypes.c_void_p(lam.data_ptr()), None, None, None) == _lib.SP6_ERR_STATE
     G.set_energy_coupling(enable=False)
     off = G.rhs(Fd)
     torch.cuda.synchronize()
