@@ -148,9 +148,11 @@ sp6_status sp6_set_scattering_kernel(sp6_grid grid, double c1, double c2);
  * formed in FP64.  sp6_adjoint_step(_stages) then transpose the step's
  * linearisation at its stage inputs (the source is nonlinear in F), and the
  * sigma gradient includes the source.  enable = 0 turns it off (the other
- * arguments are ignored).  Needs a handle created with scattering = 1 (SP6_ERR_STATE),
- * 2 <= n_eps <= 64 (SP6_ERR_SHAPE), 0 <= gamma_min < gamma_max and alpha >= 0,
- * finite (SP6_ERR_ARG).  Allocates three per-plane device arrays on first use. */
+ * arguments are ignored).  Needs a handle created with scattering = 1
+ * (SP6_ERR_STATE), 2 <= n_eps <= 64 (SP6_ERR_SHAPE), 0 <= gamma_min < gamma_max
+ * and alpha >= 0, finite (SP6_ERR_ARG).  Allocates three per-plane device arrays
+ * on first use, and two more on the first adjoint step with the coupling on;
+ * the stepping calls themselves allocate nothing for it. */
 sp6_status sp6_set_energy_coupling(sp6_grid grid, int32_t enable, double gamma_min, double gamma_max,
                                    double alpha);
 
