@@ -125,9 +125,18 @@ __global__ __launch_bounds__(FP_THREADS) void k_fp_moments(KDims d, KTab t, cons
 #pragma unroll
     for (int k = 0; k < 32; ++k) v[k] = 0.0;
     if (ok) {
+      // the column's rows in batches of eight loads in flight
       const TI* __restrict__ col = Y + pid * d.plane + m;
-      for (int i = 0; i < nT; ++i)
-        add_moments(v, sW[i] * double(col[i * NP]), sCT[i], sST[i] * cP, sST[i] * sP);
+      for (int i0 = 0; i0 < nT; i0 += 8) {
+        double f[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) f[u] = i0 + u < nT ? double(col[(i0 + u) * NP]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          if (i < nT) add_moments(v, sW[i] * f[u], sCT[i], sST[i] * cP, sST[i] * sP);
+        }
+      }
     }
     double M0, Q = 0.0;
     if constexpr (NP >= 32) {
@@ -233,10 +242,21 @@ __global__ __launch_bounds__(FP_THREADS) void k_fp_adj_moments(KDims d, KTab t, 
       const int j = int(pid >> (sh_ph + sh_th)) % d.n_r;  // radial index of the plane
       const double* __restrict__ yc = Y + pid * d.plane + m;
       const double* __restrict__ xc = X + pid * d.plane + m;
-      for (int i = 0; i < nT; ++i) {
-        add_moments(v, sW[i] * yc[i * NP], sCT[i], sST[i] * cP, sST[i] * sP);
-        const bool held = d.bc && ((j == 0 && sCT[i] > 0.0) || (j == d.n_r - 1 && sCT[i] < 0.0));
-        v[20] += held ? 0.0 : xs * xc[i * NP];
+      for (int i0 = 0; i0 < nT; i0 += 8) {
+        double fy[8], fx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          fy[u] = i0 + u < nT ? yc[(i0 + u) * NP] : 0.0;
+          fx[u] = i0 + u < nT ? xc[(i0 + u) * NP] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u;
+          if (i >= nT) continue;
+          add_moments(v, sW[i] * fy[u], sCT[i], sST[i] * cP, sST[i] * sP);
+          const bool held = d.bc && ((j == 0 && sCT[i] > 0.0) || (j == d.n_r - 1 && sCT[i] < 0.0));
+          v[20] += held ? 0.0 : xs * fx[u];
+        }
       }
     }
     if constexpr (NP >= 32) {
