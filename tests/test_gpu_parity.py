@@ -21,7 +21,8 @@ TOL = 1e-12
 # seventeen, five 16-row tiles, the last one ragged), one (eps, r) slab set of the
 # large grid's angular shape (theta lines of 64 points, 2048-point planes), and
 # the 32 x 64 position sphere on small planes (fused theta-phi tiles spanning two
-# Theta rows of a 128-byte line; odd n_eps * n_r, so the last workgroups are idle),
+# Theta rows of a 128-byte line; odd n_eps * n_r, so the last workgroups are idle)
+# and on 16 x 32 planes (two-plane workgroups of the plane pass),
 # and the smallest and largest radial lines the descriptor accepts (n_r = 3: one
 # k-step, one row tile mostly padding; n_r = 80: twenty k-steps, five full row tiles)
 SHAPES = {
@@ -37,6 +38,7 @@ SHAPES = {
     "w5_slab": small(5, n_eps=1, n_r=3),
     "s64_small": small(5, n_eps=1, n_r=3, n_Theta=8, n_Phi=16),
     "s64_ragged": small(5, n_eps=3, n_r=5, n_Theta=8, n_Phi=16),
+    "s64_mid": small(5, n_eps=1, n_r=3, n_Theta=16, n_Phi=32),
     "r3": small(3, n_eps=2, n_r=3, n_theta=2, n_phi=4, n_Theta=4, n_Phi=8),
     "r80": small(3, n_eps=1, n_r=80, n_theta=2, n_phi=4, n_Theta=4, n_Phi=8),
 }
@@ -100,7 +102,7 @@ def test_rhs_switches(bc, scat):
 
 
 @pytest.mark.parametrize("name", ["tiny", "ragged", "cfg1", "w2_reduced", "big_lines", "wide_plane", "r33", "r65",
-                                  "w5_slab", "s64_small", "s64_ragged", "r3", "r80"])
+                                  "w5_slab", "s64_small", "s64_ragged", "s64_mid", "r3", "r80"])
 def test_step(name):
     cfg = SHAPES[name]
     banner(f"step {name}")

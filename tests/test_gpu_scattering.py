@@ -10,7 +10,7 @@ import torch
 
 import synth
 from oracle import ops, step, adjoint
-from tests.gpu_util import need_gpu, maxrel, to_dev, to_host, oracle_grid, small, banner
+from tests.gpu_util import need_gpu, maxrel, to_dev, to_host, oracle_grid, small, banner, stable_dt
 
 pytestmark = pytest.mark.gpu
 
@@ -21,6 +21,8 @@ SHAPES = {
     "small": small(3, n_eps=2, n_r=9, n_theta=4, n_phi=8, n_Theta=8, n_Phi=16),
     "w3_reduced": small(3, n_eps=1, n_r=5),
     "wide_plane": small(3, n_eps=1, n_r=5, n_theta=2, n_phi=4, n_Theta=32, n_Phi=64),
+    # the 32 x 64 position sphere (fused theta-phi tiles of the large workload)
+    "sphere64": small(5, n_eps=1, n_r=3, n_Theta=8, n_Phi=16),
 }
 
 
@@ -56,13 +58,13 @@ def test_rhs(name, kname):
 
 
 @pytest.mark.parametrize("kname", ["thomson", "mixed"])
-@pytest.mark.parametrize("name", ["tiny", "small", "wide_plane"])
+@pytest.mark.parametrize("name", ["tiny", "small", "wide_plane", "sphere64"])
 def test_step_and_adjoint(name, kname):
     cfg, kern = SHAPES[name], KERNELS[kname]
     G, F, (k, s, e) = setup(cfg, kern, seed=3)
     g = oracle_grid(cfg)
     p = step.Physics(k, s, e, bc=True, scattering=True, kernel=kern)
-    dt = cfg.dt
+    dt = stable_dt(cfg)
     Fd = to_dev(F)
     G.step(Fd, dt, 3)
     err = maxrel(to_host(Fd), step.run(F, g, p, dt, 3))
