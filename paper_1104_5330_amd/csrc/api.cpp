@@ -229,14 +229,18 @@ hipError_t ensure_step_scratch(sp6_grid g) {
 }
 
 // the r, theta and phi terms of L Y (or of L^T for the transposed passes) into T
+// (paired: Y and T in the paired in-plane order, for the fused theta-phi pass of
+// the 32 x 64 sphere; the radial pass works column by column in either order)
 hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transpose, bool mask_in,
-                        double in_scale, bool* wrote, Timer* tm = nullptr, double* Tdst = nullptr) {
+                        double in_scale, bool* wrote, Timer* tm = nullptr, double* Tdst = nullptr,
+                        bool paired = false) {
   hipError_t e = hipSuccess;
   bool acc = false;
   const double sg = transpose ? -1.0 : 1.0;
   double* T = Tdst ? Tdst : g->T;
+  if (paired && !((terms & 6u) == 6u && paired_order_ok(g->d))) return hipErrorInvalidValue;
   if ((terms & 6u) == 6u && sphere_fusable(g->d, false)) {
-    e = launch_sphere(next_pass(g), g->t, Y, T, sg, mask_in, in_scale, g->stream);
+    e = launch_sphere(next_pass(g), g->t, Y, T, sg, mask_in, in_scale, g->stream, paired);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
     if (e != hipSuccess) return e;
     acc = true;
@@ -740,6 +744,12 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
     if (sp6_status st = ensure_radial_implicit(g, dt)) return st;
   const KDims& d = g->d;
   const uint32_t cols = radial_implicit ? 6u : 7u;  // without the radial term in the split step
+  // FP64 stage buffers in the paired in-plane order on the 32 x 64 sphere: the
+  // stage state, T and the accumulator of stages 2 to 4 (the fused theta-phi pass
+  // then moves one 64-byte run per tile row instead of two 32-byte runs).  Not
+  // with stored stage states (the adjoint reads them in the plain order) or the
+  // energy coupling (its moment pass reads the stage states in the plain order).
+  const bool paired = !mixed && !Ystages && !g->fp_on && paired_order_ok(d) && d.n_Ph == 2 * d.n_Th;
   if (tm) HIP_TRY(tm->mark(g->stream, -1), "event");
   for (int32_t n = 0; n < nsteps; ++n) {
     for (int s = 1; s <= 4; ++s) {
@@ -757,9 +767,10 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
         a.T = b.Tf;
       } else {
         const double* Yin = (s == 1) ? F : (Ystages ? Ystages + size_t(s - 2) * size_t(d.P) : b.Y);
-        HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm, b.T), "column passes");
+        HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm, b.T, paired && s > 1), "column passes");
         a.Yin = Yin;
         a.T = b.T;
+        if (paired) a.pair_mode = s == 1 ? 1 : (s == 4 ? 3 : 2);
       }
       void* ybuf = mixed ? static_cast<void*>(b.Yf) : static_cast<void*>(b.Y);
       if (Ystages && s <= 3) ybuf = Ystages + size_t(s - 1) * size_t(d.P);

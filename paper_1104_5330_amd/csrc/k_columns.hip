@@ -579,8 +579,9 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 // in-plane columns, closed under the DFS partner map (two runs of CW / 2 columns
 // of one Theta row, the second at Phi + pi), holds all 32 x 64 = 2048 values of
 // each column in LDS: FP64 tiles of 8 columns (132 KB, 148 KB with the
-// operator: one workgroup per CU), FP32 tiles of 16 (the mixed path, 32-byte
-// runs).  Both line directions run as MFMA products (v_mfma_f64_16x16x4f64, or
+// operator: one workgroup per CU; two 32-byte runs, or one 64-byte run when the
+// state and T are in the paired in-plane order), FP32 tiles of 16 (the mixed
+// path, 32-byte runs).  Both line directions run as MFMA products (v_mfma_f64_16x16x4f64, or
 // v_mfma_f32_16x16x4f32) on the even/odd halves of the 64-point operator:
 //   theta: P = A E, Q = B O with E, O = Y(theta_j, phi_k, c) +- Y(theta_j,
 //          phi_k + pi, c') (the DFS line of column c at phi_k and, reversed, its
@@ -633,7 +634,7 @@ struct Pair2<float> {
 template <int CW, int NW, typename TI, typename TC>
 __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI* __restrict__ Y,
                                                       TC* __restrict__ T, double coef_sign, int mask_in,
-                                                      double in_scale, int ntiles) {
+                                                      double in_scale, int ntiles, int paired) {
   using C = S64<CW, NW, TC>;
   using TI2 = typename Pair2<TI>::type;
   using TC2 = typename Pair2<TC>::type;
@@ -654,8 +655,13 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
   const int j = ej % d.n_r;
   const int hP = d.n_Ph >> 1;
   const int tpr = hP / R;
-  const int cbase = (tl / tpr) * d.n_Ph + (tl % tpr) * R;
+  const int rowb = (tl / tpr) * d.n_Ph, gR = (tl % tpr) * R;
+  const int cbase = rowb + gR;
+  // in-plane column of tile column col, and where it is stored: the same, or in
+  // the paired order (FP64 tiles, R = 4) the tile's columns side by side
   auto colc = [&](int col) { return cbase + (col & (R - 1)) + ((col & R) ? hP : 0); };
+  const int mbase = rowb + 2 * gR;
+  auto colm = [&](int col) { return paired ? mbase + col : colc(col); };
   const int64_t slab = int64_t(ej) * d.M;
   const int plane = d.plane;
   const int tid = int(threadIdx.x);
@@ -665,14 +671,14 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
   // stage the tile with loads of two neighbouring columns of a run per lane
   {
     const int q = tid % (CW / 2);
-    const int c = colc(2 * q);
+    const int c = colc(2 * q), cm = colm(2 * q);
     double s_in = in_scale;
     if (mask_in && is_inflow(d, t, j, c / d.n_Ph)) s_in = 0.0;
     TI2 v[C::PPT];
 #pragma unroll
     for (int i = 0; i < C::PPT; ++i) {
       const int p = tid + i * C::NTHR;  // pair p = combo * CW / 2 + q, combo = theta * 64 + phi
-      v[i] = *reinterpret_cast<const TI2*>(Y + (slab + int64_t(p / (CW / 2)) * plane + c));
+      v[i] = *reinterpret_cast<const TI2*>(Y + (slab + int64_t(p / (CW / 2)) * plane + cm));
     }
 #pragma unroll
     for (int i = 0; i < C::PPT; ++i) {
@@ -793,7 +799,7 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
         const int n = (ng * UH + u) * 16 + lr;
         const int l = n / CW, col = n % CW;
         const TC sc = TC(sc0 * sIs[l]);
-        const int64_t ob = slab + int64_t(l) * NPH * plane + colc(col);
+        const int64_t ob = slab + int64_t(l) * NPH * plane + colm(col);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = crow(h, v);
@@ -883,18 +889,21 @@ bool sphere64_ok(const KDims& d) { return d.n_th == 32 && d.n_ph == 64 && d.n_Ph
 
 template <int CW, int NW, typename TI, typename TC>
 hipError_t launch_sphere64_t(const KDims& d, const KTab& t, const TI* Y, TC* T, double coef_sign, bool mask_in,
-                             double in_scale, hipStream_t s) {
+                             double in_scale, hipStream_t s, bool paired = false) {
+  // the paired order groups runs of four columns: FP64 tiles only
+  if (paired && CW != 8) return hipErrorInvalidValue;
   const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
   constexpr int64_t GB = 8 * (128 / (CW / 2 * int64_t(sizeof(TI))));
   const int64_t nb = (ntiles + GB - 1) / GB * GB;
   if (nb > INT32_MAX) return hipErrorInvalidValue;
-  k_sphere64<CW, NW, TI, TC><<<unsigned(nb), 64 * NW, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale, int(ntiles));
+  k_sphere64<CW, NW, TI, TC><<<unsigned(nb), 64 * NW, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale, int(ntiles),
+                                                              int(paired));
   return hipGetLastError();
 }
 
 hipError_t launch_sphere64(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign, bool mask_in,
-                           double in_scale, hipStream_t s) {
-  return launch_sphere64_t<8, 16>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
+                           double in_scale, hipStream_t s, bool paired) {
+  return launch_sphere64_t<8, 16>(d, t, Y, T, coef_sign, mask_in, in_scale, s, paired);
 }
 
 // FP32 tiles of 16 columns (32-byte runs of an FP32 row, 133 KB of LDS): 3.89 ms
@@ -955,9 +964,12 @@ hipError_t launch_theta_mixed(const KDims& d, const KTab& t, const void* Y, bool
 
 bool sphere_fusable(const KDims& d, bool mixed) { return sphere_cw(d) > 0 || sphere64_ok(d); }
 
+bool paired_order_ok(const KDims& d) { return sphere64_ok(d); }
+
 hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
-                         bool mask_in, double in_scale, hipStream_t s) {
-  if (sphere64_ok(d)) return launch_sphere64(d, t, Y, T, coef_sign, mask_in, in_scale, s);
+                         bool mask_in, double in_scale, hipStream_t s, bool paired) {
+  if (sphere64_ok(d)) return launch_sphere64(d, t, Y, T, coef_sign, mask_in, in_scale, s, paired);
+  if (paired) return hipErrorInvalidValue;
   switch (sphere_cw(d)) {
     case 8: return launch_sphere_n<8, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);
     case 16: return launch_sphere_n<16, double, double>(d, t, Y, T, coef_sign, mask_in, in_scale, s);

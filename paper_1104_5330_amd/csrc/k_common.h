@@ -44,6 +44,22 @@ SP6_DEV void eo_pairs(const TT* __restrict__ tab, int i0, const T (&v)[L], Emit&
 }
 
 SP6_DEV int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+// p advanced by b bytes (a 32-bit lane offset added to a wave-uniform pointer)
+template <typename T>
+SP6_DEV T* byte_off(T* p, uint32_t b) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(p) + b);
+}
+template <typename T>
+SP6_DEV const T* byte_off(const T* p, uint32_t b) {
+  return reinterpret_cast<const T*>(reinterpret_cast<const char*>(p) + b);
+}
+// x, opaque to the optimiser (no instruction): keeps a lane offset from being
+// folded into a 64-bit lane address hoisted out of a loop, so that a uniform row
+// pointer plus this 32-bit offset is formed at the access
+SP6_DEV uint32_t lane_opaque(uint32_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
 
 // Streaming access: data read or written once per pass.  SP6_NT selects which
 // global accesses carry the nontemporal hint (bits below).  Measured on the

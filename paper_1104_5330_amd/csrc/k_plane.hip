@@ -226,9 +226,17 @@ constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes)
 // Yin = F + dt/2 k1 and ysrc = F give F + dt/6 k1 = ysrc + (Yin - ysrc) / 3, so
 // stage 1 need not write the accumulator); 4 on the accumulator source itself
 // (Adams-Bashforth, whose history H is both: loaded once)
-template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN>
+// PM: the paired in-plane order (StageArgs::pair_mode).  With PM 2 and 3 a
+// thread's points are paired positions: it reads the stage state, T and the
+// accumulator source and writes the paired outputs at them, stages its values in
+// LDS at their columns' plain places, and reads y (PM 2) or writes the
+// accumulator destination (PM 3) in the plain order at a lane offset; with PM 1
+// its points are plain and only ynext is written at the paired position.
+template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN, int PM = 0>
 __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, YM, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
+  static_assert(PM == 0 || (C::NF >= 16 && C::NTHR % C::NF == 0 && sizeof(TY) == 8 && sizeof(TO) == 8),
+                "the paired order: FP64, n_Phi >= 16, the points tid + q NTHR of a thread share a column");
   constexpr bool NY = YM == 1 || YM == 2, YR = YM == 2, YA = YM == 4;
   static_assert(!YR || !NA, "the accumulator base is either loaded or recovered");
   static_assert(!YA || NA, "y is the loaded accumulator");
@@ -296,6 +304,20 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   auto gid = [&](int k) { return d.rev ? ngroups - 1 - k : k; };
   const bool apply = a.mode == PM_APPLY, scat = !apply && d.scattering;
   const int sh_ph = __builtin_ctz(d.n_ph), sh_th = __builtin_ctz(d.n_th);
+  // paired order: the column m of the thread's points, the LDS (and plain-order)
+  // offset of its points (PM 2, 3) and the byte offset of its plain-order or
+  // paired-order operand
+  int lofs = 0;
+  uint32_t bo_pm = 0;
+  if constexpr (PM != 0) {
+    const int m = tid & (C::NF - 1);
+    if constexpr (PM == 1)
+      bo_pm = uint32_t(tid + paired_pos(m, C::NF / 2) - m) * 8u;
+    else {
+      lofs = paired_phi(m, C::NF / 2) - m;
+      bo_pm = uint32_t(tid + lofs) * 8u;
+    }
+  }
   auto load_group = [&](int g, TY* yi, TO* ti, double* ai, double* yo) {
     const int plane0 = g * C::NPW;
     const int64_t base = int64_t(plane0) * C::PLANE;
@@ -303,6 +325,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
     const TO* __restrict__ Tb = Tin + base;
     const double* __restrict__ Ab = a.accsrc + base;
     const double* __restrict__ Xb = a.ysrc + base;
+    const uint32_t bx = PM == 2 ? lane_opaque(bo_pm) : 0u;
     if (plane0 + C::NPW <= npl) {
 #pragma unroll
       for (int q = 0; q < C::PPT; ++q) {
@@ -310,7 +333,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         yi[q] = ld_stream<NT_PLANE_LD>(Yb + p);
         ti[q] = needT ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
         if constexpr (NA && (NY || YA)) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
-        if constexpr (NY) yo[q] = ld_stream<NT_PLANE_LDA>(Xb + p);
+        if constexpr (NY) {
+          if constexpr (PM == 2)
+            yo[q] = ld_stream<NT_PLANE_LDA>(byte_off(Xb + q * C::NTHR, bx));
+          else
+            yo[q] = ld_stream<NT_PLANE_LDA>(Xb + p);
+        }
       }
     } else {
 #pragma unroll
@@ -320,7 +348,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         yi[q] = ok ? ld_stream<NT_PLANE_LD>(Yb + p) : TY(0);
         ti[q] = (ok && needT) ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
         if constexpr (NA && (NY || YA)) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
-        if constexpr (NY) yo[q] = ok ? ld_stream<NT_PLANE_LDA>(Xb + p) : 0.0;
+        if constexpr (NY) {
+          if constexpr (PM == 2)
+            yo[q] = ok ? ld_stream<NT_PLANE_LDA>(byte_off(Xb + q * C::NTHR, bx)) : 0.0;
+          else
+            yo[q] = ok ? ld_stream<NT_PLANE_LDA>(Xb + p) : 0.0;
+        }
       }
     }
   };
@@ -362,7 +395,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
     const int grp = gid(kk);
     const int plane0 = grp * C::NPW;
 #pragma unroll
-    for (int q = 0; q < C::PPT; ++q) sY[C::lds(tid + q * C::NTHR)] = yin[q];
+    for (int q = 0; q < C::PPT; ++q) sY[C::lds(tid + q * C::NTHR) + lofs] = yin[q];
     if constexpr (MEAN_STAGED) {
       if (scat) {
         static_assert(C::PLANE % C::NTHR == 0, "a thread's staged point q lies in plane q NTHR / PLANE");
@@ -596,13 +629,14 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
     __syncthreads();
 
     const int64_t base = int64_t(plane0) * C::PLANE;
+    const uint32_t bs = PM == 1 || PM == 3 ? lane_opaque(bo_pm) : 0u;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int p = tid + q * C::NTHR;
       const int pl = p / C::PLANE;
       if (plane0 + pl >= npl) continue;
       const int64_t gp = base + uint32_t(p);
-      const int lp = C::lds(p);
+      const int lp = C::lds(p) + lofs;
       double LY = double(tv[q]);
       if (useTh) LY += double(sR[0][lp]);
       if (usePh) LY += double(sR[1][lp]);
@@ -614,7 +648,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
       const double Yv = double(sY[lp]);
       double inscat = pi.mean;
       if constexpr (AN) {
-        const int iTh = C::row_of(tid, q), m = p % C::NF;
+        const int iTh = C::row_of(tid, q), m = p % C::NF + lofs;
         inscat = phase_contract(cf, sMo[pl], sCT[iTh], sTh[iTh] * sCP[m], sTh[iTh] * sPh[m]);
       }
       double k = -LY + pi.eta - (pi.kappa + pi.sigma) * Yv + pi.sigma * inscat;
@@ -628,8 +662,17 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
       if constexpr (NY) yb = yv[q];
       if constexpr (YR) ab = yb + (Yv - yb) * (1.0 / 3.0);
       if constexpr (YA) yb = ab;
-      if (a.accdst) st_stream<NT_PLANE_STA>(a.accdst + gp, ab + a.cb * k);
-      if (ynext) st_stream<NT_PLANE_ST>(ynext + gp, TO(yb + a.cn * k));
+      if constexpr (PM == 3) {
+        if (a.accdst)
+          st_stream<NT_PLANE_STA>(byte_off(a.accdst + (base + q * C::NTHR), bs), ab + a.cb * k);
+      } else {
+        if (a.accdst) st_stream<NT_PLANE_STA>(a.accdst + gp, ab + a.cb * k);
+      }
+      if constexpr (PM == 1) {
+        if (ynext) st_stream<NT_PLANE_ST>(byte_off(ynext + (base + q * C::NTHR), bs), TO(yb + a.cn * k));
+      } else {
+        if (ynext) st_stream<NT_PLANE_ST>(ynext + gp, TO(yb + a.cn * k));
+      }
     }
     __syncthreads();
   }
@@ -996,11 +1039,29 @@ unsigned persistent_blocks(const KDims& d, K kernel, int threads, int64_t work) 
   return unsigned(work < cap ? work : cap);
 }
 
-template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN>
+template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN, int PM = 0>
 void launch_plane_t(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   const int ng = int((d.nplanes + PC<NT>::NPW - 1) / PC<NT>::NPW);
-  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, YM, TY, TO, TC, AN>, PC<NT>::NTHR, ng);
-  k_plane<NT, NA, YM, TY, TO, TC, AN><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
+  const unsigned nb = persistent_blocks(d, k_plane<NT, NA, YM, TY, TO, TC, AN, PM>, PC<NT>::NTHR, ng);
+  k_plane<NT, NA, YM, TY, TO, TC, AN, PM><<<nb, PC<NT>::NTHR, 0, s>>>(d, t, c, a, ng);
+}
+
+// the FP64 RK4 stages in the paired order (launch_plane has checked the shape,
+// the stage form of each mode and that the stage matches the mode)
+template <int NT, bool AN>
+void launch_plane_paired(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
+  if constexpr (2 * NT >= 16) {
+    switch (a.pair_mode) {
+      case 1: launch_plane_t<NT, false, 0, double, double, double, AN, 1>(d, t, c, a, s); break;
+      case 2:
+        if (a.accrec)
+          launch_plane_t<NT, false, 2, double, double, double, AN, 2>(d, t, c, a, s);
+        else
+          launch_plane_t<NT, true, 1, double, double, double, AN, 2>(d, t, c, a, s);
+        break;
+      default: launch_plane_t<NT, true, 0, double, double, double, AN, 3>(d, t, c, a, s); break;
+    }
+  }
 }
 
 template <int NT, typename TY, typename TO, typename TC>
@@ -1008,6 +1069,11 @@ void launch_plane_nt(const KDims& d, const KTab& t, const KCoef& c, const StageA
   const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
   const bool an = d.scattering && c.aniso && a.mode != PM_APPLY;
   if constexpr (sizeof(TY) == 8 && sizeof(TO) == 8) {
+    if (a.pair_mode) {
+      if (an) launch_plane_paired<NT, true>(d, t, c, a, s);
+      else launch_plane_paired<NT, false>(d, t, c, a, s);
+      return;
+    }
     if (na && ny && a.accsrc == a.ysrc) {  // y is the accumulator source: load it once (AB2 step 3 % faster)
       if (an) launch_plane_t<NT, true, 4, TY, TO, TC, true>(d, t, c, a, s);
       else launch_plane_t<NT, true, 4, TY, TO, TC, false>(d, t, c, a, s);
@@ -1044,6 +1110,20 @@ void launch_plane_n(const KDims& d, const KTab& t, const KCoef& c, const StageAr
 
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   if (a.accrec && (a.mixed || a.mode != PM_STAGE || a.accsrc || !a.ysrc)) return hipErrorInvalidValue;
+  if (a.pair_mode) {
+    // the FP64 RK4 stage forms: 1 (no accumulator, no y), 2 (stage 2: accumulator
+    // recovered from y; stage 3: accumulator and y), 3 (accumulator, no y, no ynext)
+    const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
+    bool form = false;
+    switch (a.pair_mode) {
+      case 1: form = !na && !ny && !a.accdst && a.ynext; break;
+      case 2: form = ny && a.accdst && a.ynext && (a.accrec ? !na : (na && a.accsrc != a.ysrc)); break;
+      case 3: form = na && !ny && a.accdst && !a.ynext; break;
+      default: break;
+    }
+    if (!form || a.mixed || a.mode != PM_STAGE || !paired_order_ok(d) || d.n_Ph != 2 * d.n_Th)
+      return hipErrorInvalidValue;
+  }
   switch (d.n_Th) {
 #define CASE(N)                          \
   case N:                                \

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/sp6d.h"
+#include "paired_order.h"
 
 // largest supported n_r (descriptor validation; per-workgroup LDS tables)
 constexpr int SP6_MAX_NR = 80;
@@ -118,7 +119,16 @@ struct StageArgs {
   uint32_t terms;        // bit 3 Theta, bit 4 Phi
   int mixed;             // 0: FP64 path; 1: mixed path
   int yin_f32;           // mixed path: Yin is FP32
+  // FP64 RK4 stages on the 32 x 64 sphere (paired_order_ok), operands in the
+  // paired in-plane order (paired_order.h): 0 none; 1 ynext (stage 1); 2 Yin, T, accsrc,
+  // accdst and ynext, ysrc plain (stages 2, 3); 3 Yin, T and accsrc, accdst
+  // plain (stage 4)
+  int pair_mode;
 };
+
+// the 32 x 64 position sphere with n_Phi >= 16: where the fused theta-phi tiles of
+// eight FP64 columns apply, and with them the paired order
+bool paired_order_ok(const KDims& d);
 
 hipError_t launch_phi(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
                       double coef_sign, bool mask_in, double in_scale, hipStream_t s);
@@ -128,8 +138,9 @@ hipError_t launch_theta(const KDims& d, const KTab& t, const double* Y, double* 
 // n_theta <= 16, and for the 32 x 64 sphere with n_Phi >= 16; the separate passes
 // take every other shape
 bool sphere_fusable(const KDims& d, bool mixed);
+// paired: Y and T in the paired in-plane order (paired_order_ok only)
 hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
-                         bool mask_in, double in_scale, hipStream_t s);
+                         bool mask_in, double in_scale, hipStream_t s, bool paired = false);
 hipError_t launch_sphere_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T,
                                hipStream_t s);
 hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,

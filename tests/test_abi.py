@@ -140,3 +140,47 @@ int main() {
     subprocess.run([cxx, "-std=c++17", "-O1", "-Wall", "-I", inc, str(src), "-o", str(exe)], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout
+
+
+def test_paired_order_host_build(tmp_path, root):
+    # the paired in-plane order of the FP64 stage buffers (csrc/paired_order.h),
+    # built on its own with the host compiler: a permutation inside each row with
+    # its inverse, and every fused theta-phi tile of eight columns (four at Phi,
+    # four at Phi + pi) one contiguous run in the order
+    src = tmp_path / "p.cpp"
+    src.write_text(r'''
+#include "paired_order.h"
+#include <cstdio>
+int main() {
+  int bad = 0;
+  for (int nPh = 16; nPh <= 64; nPh *= 2) {
+    const int hP = nPh / 2;
+    int seen[64] = {0};
+    for (int phi = 0; phi < nPh; ++phi) {
+      const int p = paired_pos(phi, hP);
+      bad += p < 0 || p >= nPh;
+      if (p >= 0 && p < nPh) seen[p]++;
+      bad += paired_phi(p, hP) != phi;
+    }
+    for (int p = 0; p < nPh; ++p) bad += seen[p] != 1;
+    for (int g = 0; g < hP / 4; ++g)
+      for (int col = 0; col < 8; ++col) {
+        const int phi = 4 * g + (col & 3) + ((col & 4) ? hP : 0);
+        bad += paired_pos(phi, hP) != 8 * g + col;
+      }
+  }
+  static_assert(paired_pos(37, 32) == 12 + 1, "Phi = 37 of 64: group 1 of the second half");
+  std::printf("%d\n", bad);
+  return bad;
+}
+''')
+    import shutil
+    import subprocess
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    inc = os.path.join(root, "paper_1104_5330_amd", "csrc")
+    exe = tmp_path / "p"
+    subprocess.run([cxx, "-std=c++17", "-O1", "-Wall", "-I", inc, str(src), "-o", str(exe)], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0 and r.stdout.strip() == "0", r.stdout + r.stderr
