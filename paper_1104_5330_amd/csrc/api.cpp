@@ -750,8 +750,13 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
   // with stored stage states (the adjoint reads them in the plain order) or the
   // energy coupling (its moment pass reads the stage states in the plain order).
   const bool paired = !mixed && !Ystages && !g->fp_on && paired_order_ok(d) && d.n_Ph == 2 * d.n_Th;
+  // and F itself between the steps of one call (the last step writes it in the
+  // plain order again), unless the filter runs between steps (its plane and theta
+  // passes read the plain order)
+  const bool keepF = paired && !g->desc.filter;
   if (tm) HIP_TRY(tm->mark(g->stream, -1), "event");
   for (int32_t n = 0; n < nsteps; ++n) {
+    const bool Fp = keepF && n > 0;  // F holds the paired order
     for (int s = 1; s <= 4; ++s) {
       bool wrote = false;
       StageArgs a{};
@@ -767,10 +772,14 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
         a.T = b.Tf;
       } else {
         const double* Yin = (s == 1) ? F : (Ystages ? Ystages + size_t(s - 2) * size_t(d.P) : b.Y);
-        HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm, b.T, paired && s > 1), "column passes");
+        HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm, b.T, paired && (s > 1 || Fp)),
+                "column passes");
         a.Yin = Yin;
         a.T = b.T;
-        if (paired) a.pair_mode = s == 1 ? 1 : (s == 4 ? 3 : 2);
+        if (paired) {
+          a.pair_mode = s == 1 ? (Fp ? 2 : 1) : (s == 4 ? 3 : 2);
+          a.pair_all = s == 1 ? 1 : (s == 4 ? (keepF && n + 1 < nsteps) : Fp);
+        }
       }
       void* ybuf = mixed ? static_cast<void*>(b.Yf) : static_cast<void*>(b.Y);
       if (Ystages && s <= 3) ybuf = Ystages + size_t(s - 1) * size_t(d.P);

@@ -230,8 +230,9 @@ constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes)
 // thread's points are paired positions: it reads the stage state, T and the
 // accumulator source and writes the paired outputs at them, stages its values in
 // LDS at their columns' plain places, and reads y (PM 2) or writes the
-// accumulator destination (PM 3) in the plain order at a lane offset; with PM 1
-// its points are plain and only ynext is written at the paired position.
+// accumulator destination (PM 3) in the plain order at a lane offset, or at its
+// points too when a.pair_all says they are paired as well; with PM 1 its points
+// are plain and only ynext is written at the paired position.
 template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN, int PM = 0>
 __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, YM, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
       bo_pm = uint32_t(tid + paired_pos(m, C::NF / 2) - m) * 8u;
     else {
       lofs = paired_phi(m, C::NF / 2) - m;
-      bo_pm = uint32_t(tid + lofs) * 8u;
+      bo_pm = uint32_t(tid + (a.pair_all ? 0 : lofs)) * 8u;
     }
   }
   auto load_group = [&](int g, TY* yi, TO* ti, double* ai, double* yo) {
@@ -1056,8 +1057,10 @@ void launch_plane_paired(const KDims& d, const KTab& t, const KCoef& c, const St
       case 2:
         if (a.accrec)
           launch_plane_t<NT, false, 2, double, double, double, AN, 2>(d, t, c, a, s);
-        else
+        else if (a.accsrc)
           launch_plane_t<NT, true, 1, double, double, double, AN, 2>(d, t, c, a, s);
+        else
+          launch_plane_t<NT, false, 0, double, double, double, AN, 2>(d, t, c, a, s);
         break;
       default: launch_plane_t<NT, true, 0, double, double, double, AN, 3>(d, t, c, a, s); break;
     }
@@ -1111,13 +1114,18 @@ void launch_plane_n(const KDims& d, const KTab& t, const KCoef& c, const StageAr
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   if (a.accrec && (a.mixed || a.mode != PM_STAGE || a.accsrc || !a.ysrc)) return hipErrorInvalidValue;
   if (a.pair_mode) {
-    // the FP64 RK4 stage forms: 1 (no accumulator, no y), 2 (stage 2: accumulator
-    // recovered from y; stage 3: accumulator and y), 3 (accumulator, no y, no ynext)
+    // the FP64 RK4 stage forms: 1 (no accumulator, no y), 2 (stage 1 on a
+    // paired state: no accumulator, no y; stage 2: accumulator recovered from y;
+    // stage 3: accumulator and y), 3 (accumulator, no y, no ynext)
     const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
+    const bool s1 = !na && !ny && !a.accdst && a.ynext;
     bool form = false;
     switch (a.pair_mode) {
-      case 1: form = !na && !ny && !a.accdst && a.ynext; break;
-      case 2: form = ny && a.accdst && a.ynext && (a.accrec ? !na : (na && a.accsrc != a.ysrc)); break;
+      case 1: form = s1; break;
+      case 2:
+        form = (s1 && a.pair_all) ||
+               (ny && a.accdst && a.ynext && (a.accrec ? !na : (na && a.accsrc != a.ysrc)));
+        break;
       case 3: form = na && !ny && a.accdst && !a.ynext; break;
       default: break;
     }

@@ -120,10 +120,12 @@ struct StageArgs {
   int mixed;             // 0: FP64 path; 1: mixed path
   int yin_f32;           // mixed path: Yin is FP32
   // FP64 RK4 stages on the 32 x 64 sphere (paired_order_ok), operands in the
-  // paired in-plane order (paired_order.h): 0 none; 1 ynext (stage 1); 2 Yin, T, accsrc,
-  // accdst and ynext, ysrc plain (stages 2, 3); 3 Yin, T and accsrc, accdst
-  // plain (stage 4)
+  // paired in-plane order (paired_order.h): 0 none; 1 ynext (stage 1 on the
+  // caller's plain state); 2 Yin, T, accsrc, accdst and ynext, ysrc plain
+  // (stages 2, 3, and stage 1 on a paired state); 3 Yin, T and accsrc, accdst
+  // plain (stage 4).  pair_all (modes 2, 3): ysrc or accdst paired as well.
   int pair_mode;
+  int pair_all;
 };
 
 // the 32 x 64 position sphere with n_Phi >= 16: where the fused theta-phi tiles of
