@@ -180,7 +180,10 @@ sp6_status sp6_apply_LT(sp6_grid grid, const double* G, double* out);
 sp6_status sp6_rhs(sp6_grid grid, const double* F, double* out);
 
 /* nsteps >= 0 classical RK4 steps of size dt > 0, in place on F (then the
- * filter if enabled).  Needs coefficients. */
+ * filter if enabled).  Needs coefficients.  F is in the C-order state layout when the
+ * call returns; between the steps of one call on the 32 x 64 position sphere
+ * (FP64, no filter, no energy coupling) it is held with every Theta row of a
+ * plane reordered, so after an error mid-call its contents are unspecified. */
 sp6_status sp6_step(sp6_grid grid, double* F, double dt, int32_t nsteps);
 
 /* nsteps >= 0 steps of the split scheme of App. B, in place on F: one RK4 step of
