@@ -269,13 +269,15 @@ hipError_t column_terms(sp6_grid g, const double* Y, uint32_t terms, bool transp
 }
 
 // mixed path: the r, theta and phi terms of L Y in FP32 (Y stored in FP64 or FP32)
+// (paired: the FP32 stage copy and T in the paired in-plane order)
 hipError_t column_terms_mixed(sp6_grid g, const void* Y, bool y_f32, uint32_t terms, bool* wrote,
-                              Timer* tm = nullptr, float* Tdst = nullptr) {
+                              Timer* tm = nullptr, float* Tdst = nullptr, bool paired = false) {
   hipError_t e = hipSuccess;
   bool acc = false;
   float* Tf = Tdst ? Tdst : g->Tf;
+  if (paired && !((terms & 6u) == 6u && y_f32 && paired_order_ok(g->d))) return hipErrorInvalidValue;
   if ((terms & 6u) == 6u && sphere_fusable(g->d, true)) {
-    e = launch_sphere_mixed(next_pass(g), g->t, Y, y_f32, Tf, g->stream);
+    e = launch_sphere_mixed(next_pass(g), g->t, Y, y_f32, Tf, g->stream, paired);
     if (e == hipSuccess && tm) e = tm->mark(g->stream, KC_SPHERE);
     if (e != hipSuccess) return e;
     acc = true;
@@ -744,16 +746,17 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
     if (sp6_status st = ensure_radial_implicit(g, dt)) return st;
   const KDims& d = g->d;
   const uint32_t cols = radial_implicit ? 6u : 7u;  // without the radial term in the split step
-  // FP64 stage buffers in the paired in-plane order on the 32 x 64 sphere: the
-  // stage state, T and the accumulator of stages 2 to 4 (the fused theta-phi pass
-  // then moves one 64-byte run per tile row instead of two 32-byte runs).  Not
-  // with stored stage states (the adjoint reads them in the plain order) or the
-  // energy coupling (its moment pass reads the stage states in the plain order).
-  const bool paired = !mixed && !Ystages && !g->fp_on && paired_order_ok(d) && d.n_Ph == 2 * d.n_Th;
-  // and F itself between the steps of one call (the last step writes it in the
-  // plain order again), unless the filter runs between steps (its plane and theta
-  // passes read the plain order)
-  const bool keepF = paired && !g->desc.filter;
+  // Stage buffers in the paired in-plane order on the 32 x 64 sphere: the stage
+  // state, T and (FP64) the accumulator of stages 2 to 4 (the fused theta-phi pass
+  // then moves one 64-byte run per tile row instead of two 32-byte runs; on the
+  // mixed path the FP32 stage copy and T).  Not with stored stage states (the
+  // adjoint reads them in the plain order) or the energy coupling (its moment
+  // pass reads the stage states in the plain order).
+  const bool paired = !Ystages && !g->fp_on && paired_order_ok(d) && d.n_Ph == 2 * d.n_Th;
+  // and (FP64) F itself between the steps of one call (the last step writes it in
+  // the plain order again), unless the filter runs between steps (its plane and
+  // theta passes read the plain order)
+  const bool keepF = paired && !mixed && !g->desc.filter;
   if (tm) HIP_TRY(tm->mark(g->stream, -1), "event");
   for (int32_t n = 0; n < nsteps; ++n) {
     const bool Fp = keepF && n > 0;  // F holds the paired order
@@ -766,10 +769,11 @@ sp6_status run_steps(sp6_grid g, double* F, double dt, int32_t nsteps, Timer* tm
       if (mixed) {
         // stage 1 reads the FP64 state; later stages the FP32 stage copy
         const void* Yin = (s == 1) ? static_cast<const void*>(F) : static_cast<const void*>(b.Yf);
-        HIP_TRY(column_terms_mixed(g, Yin, s != 1, cols, &wrote, tm, b.Tf), "column passes");
+        HIP_TRY(column_terms_mixed(g, Yin, s != 1, cols, &wrote, tm, b.Tf, paired && s > 1), "column passes");
         a.Yin = Yin;
         a.yin_f32 = s != 1;
         a.T = b.Tf;
+        if (paired) a.pair_mode = s == 1 ? 1 : (s == 4 ? 3 : 2);
       } else {
         const double* Yin = (s == 1) ? F : (Ystages ? Ystages + size_t(s - 2) * size_t(d.P) : b.Y);
         HIP_TRY(column_terms(g, Yin, cols, false, false, 1.0, &wrote, tm, b.T, paired && (s > 1 || Fp)),

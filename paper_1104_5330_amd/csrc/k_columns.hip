@@ -658,7 +658,7 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
   const int rowb = (tl / tpr) * d.n_Ph, gR = (tl % tpr) * R;
   const int cbase = rowb + gR;
   // in-plane column of tile column col, and where it is stored: the same, or in
-  // the paired order (FP64 tiles, R = 4) the tile's columns side by side
+  // the paired order (groups of R columns) the tile's columns side by side
   auto colc = [&](int col) { return cbase + (col & (R - 1)) + ((col & R) ? hP : 0); };
   const int mbase = rowb + 2 * gR;
   auto colm = [&](int col) { return paired ? mbase + col : colc(col); };
@@ -890,8 +890,10 @@ bool sphere64_ok(const KDims& d) { return d.n_th == 32 && d.n_ph == 64 && d.n_Ph
 template <int CW, int NW, typename TI, typename TC>
 hipError_t launch_sphere64_t(const KDims& d, const KTab& t, const TI* Y, TC* T, double coef_sign, bool mask_in,
                              double in_scale, hipStream_t s, bool paired = false) {
-  // the paired order groups runs of four columns: FP64 tiles only
-  if (paired && CW != 8) return hipErrorInvalidValue;
+  // the paired order of a buffer groups runs of R = CW / 2 columns: 4 for the FP64
+  // state (CW = 8), 8 for the FP32 stage copy (CW = 16); an FP64 state read by
+  // FP32 tiles is the caller's state, in the plain order
+  if (paired && (CW / 2 != (sizeof(TI) == 8 ? 4 : 8) || sizeof(TC) != sizeof(TI))) return hipErrorInvalidValue;
   const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
   constexpr int64_t GB = 8 * (128 / (CW / 2 * int64_t(sizeof(TI))));
   const int64_t nb = (ntiles + GB - 1) / GB * GB;
@@ -909,9 +911,10 @@ hipError_t launch_sphere64(const KDims& d, const KTab& t, const double* Y, doubl
 // FP32 tiles of 16 columns (32-byte runs of an FP32 row, 133 KB of LDS): 3.89 ms
 // per launch on the 4-group large grid, against 3.95 for 8-column tiles (16-byte
 // runs, two workgroups per CU) and 4.44 for the separate theta and phi passes
-hipError_t launch_sphere64_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, hipStream_t s) {
-  return y_f32 ? launch_sphere64_t<16, 16>(d, t, static_cast<const float*>(Y), T, 1.0, false, 1.0, s)
-               : launch_sphere64_t<16, 16>(d, t, static_cast<const double*>(Y), T, 1.0, false, 1.0, s);
+hipError_t launch_sphere64_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T, hipStream_t s,
+                                 bool paired) {
+  return y_f32 ? launch_sphere64_t<16, 16>(d, t, static_cast<const float*>(Y), T, 1.0, false, 1.0, s, paired)
+               : launch_sphere64_t<16, 16>(d, t, static_cast<const double*>(Y), T, 1.0, false, 1.0, s, paired);
 }
 
 template <int NTH, int CW, typename TI, typename TC>
@@ -978,8 +981,9 @@ hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double*
 }
 
 hipError_t launch_sphere_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T,
-                               hipStream_t s) {
-  if (sphere64_ok(d)) return launch_sphere64_mixed(d, t, Y, y_f32, T, s);
+                               hipStream_t s, bool paired) {
+  if (sphere64_ok(d)) return launch_sphere64_mixed(d, t, Y, y_f32, T, s, paired);
+  if (paired) return hipErrorInvalidValue;
   switch (sphere_cw(d)) {
     case 8:
       return y_f32 ? launch_sphere_n<8, float, float>(d, t, Y, T, 1.0, false, 1.0, s)

@@ -232,12 +232,16 @@ constexpr int plane_waves_per_eu(int nt, bool na, int ym, bool an, int tc_bytes)
 // LDS at their columns' plain places, and reads y (PM 2) or writes the
 // accumulator destination (PM 3) in the plain order at a lane offset, or at its
 // points too when a.pair_all says they are paired as well; with PM 1 its points
-// are plain and only ynext is written at the paired position.
+// are plain and only ynext is written at the paired position.  On the mixed path
+// (FP32 T and ynext: groups of eight columns) the FP64 accumulator stays in the
+// plain order and is read and written at the same lane offset as y.
 template <int NT, bool NA, int YM, typename TY, typename TO, typename TC, bool AN, int PM = 0>
 __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu(NT, NA, YM, AN, sizeof(TC))))) void k_plane(KDims d, KTab t, KCoef cf, StageArgs a, int ngroups) {
   using C = PC<NT>;
-  static_assert(PM == 0 || (C::NF >= 16 && C::NTHR % C::NF == 0 && sizeof(TY) == 8 && sizeof(TO) == 8),
-                "the paired order: FP64, n_Phi >= 16, the points tid + q NTHR of a thread share a column");
+  constexpr bool MIX = sizeof(TO) == 4;   // mixed path
+  constexpr int PG = MIX ? 8 : 4;         // paired-order group (paired_order.h)
+  static_assert(PM == 0 || (C::NF >= 2 * PG && C::NTHR % C::NF == 0 && (MIX || sizeof(TY) == 8)),
+                "the paired order: n_Phi / 2 a multiple of the group, the points tid + q NTHR of a thread share a column");
   constexpr bool NY = YM == 1 || YM == 2, YR = YM == 2, YA = YM == 4;
   static_assert(!YR || !NA, "the accumulator base is either loaded or recovered");
   static_assert(!YA || NA, "y is the loaded accumulator");
@@ -313,9 +317,9 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
   if constexpr (PM != 0) {
     const int m = tid & (C::NF - 1);
     if constexpr (PM == 1)
-      bo_pm = uint32_t(tid + paired_pos(m, C::NF / 2) - m) * 8u;
+      bo_pm = uint32_t(tid + paired_pos(m, C::NF / 2, PG) - m) * uint32_t(sizeof(TO));
     else {
-      lofs = paired_phi(m, C::NF / 2) - m;
+      lofs = paired_phi(m, C::NF / 2, PG) - m;
       bo_pm = uint32_t(tid + (a.pair_all ? 0 : lofs)) * 8u;
     }
   }
@@ -333,7 +337,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const uint32_t p = uint32_t(tid + q * C::NTHR);
         yi[q] = ld_stream<NT_PLANE_LD>(Yb + p);
         ti[q] = needT ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && (NY || YA)) ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
+        if constexpr (NA && (NY || YA)) {
+          if constexpr (PM == 2 && MIX)
+            ai[q] = ld_stream<NT_PLANE_LDA>(byte_off(Ab + q * C::NTHR, bx));
+          else
+            ai[q] = ld_stream<NT_PLANE_LDA>(Ab + p);
+        }
         if constexpr (NY) {
           if constexpr (PM == 2)
             yo[q] = ld_stream<NT_PLANE_LDA>(byte_off(Xb + q * C::NTHR, bx));
@@ -348,7 +357,12 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
         const bool ok = plane0 + int(p) / C::PLANE < npl;
         yi[q] = ok ? ld_stream<NT_PLANE_LD>(Yb + p) : TY(0);
         ti[q] = (ok && needT) ? ld_stream<NT_PLANE_LD>(Tb + p) : TO(0);
-        if constexpr (NA && (NY || YA)) ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
+        if constexpr (NA && (NY || YA)) {
+          if constexpr (PM == 2 && MIX)
+            ai[q] = ok ? ld_stream<NT_PLANE_LDA>(byte_off(Ab + q * C::NTHR, bx)) : 0.0;
+          else
+            ai[q] = ok ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
+        }
         if constexpr (NY) {
           if constexpr (PM == 2)
             yo[q] = ok ? ld_stream<NT_PLANE_LDA>(byte_off(Xb + q * C::NTHR, bx)) : 0.0;
@@ -438,10 +452,14 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
     }
     if constexpr (NA && !NA_AHEAD) {
       const double* __restrict__ Ab = a.accsrc + int64_t(plane0) * C::PLANE;
+      const uint32_t ba = PM == 3 && MIX ? lane_opaque(bo_pm) : 0u;
 #pragma unroll
       for (int q = 0; q < C::PPT; ++q) {
         const uint32_t p = uint32_t(tid + q * C::NTHR);
-        av[q] = plane0 + int(p) / C::PLANE < npl ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
+        if constexpr (PM == 3 && MIX)
+          av[q] = plane0 + int(p) / C::PLANE < npl ? ld_stream<NT_PLANE_LDA>(byte_off(Ab + q * C::NTHR, ba)) : 0.0;
+        else
+          av[q] = plane0 + int(p) / C::PLANE < npl ? ld_stream<NT_PLANE_LDA>(Ab + p) : 0.0;
       }
     }
     if (kk + gstep < ngroups) {
@@ -630,7 +648,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
     __syncthreads();
 
     const int64_t base = int64_t(plane0) * C::PLANE;
-    const uint32_t bs = PM == 1 || PM == 3 ? lane_opaque(bo_pm) : 0u;
+    const uint32_t bs = PM == 1 || PM == 3 || (PM == 2 && MIX) ? lane_opaque(bo_pm) : 0u;
 #pragma unroll
     for (int q = 0; q < C::PPT; ++q) {
       const int p = tid + q * C::NTHR;
@@ -663,7 +681,7 @@ __global__ __launch_bounds__(PC<NT>::NTHR) __attribute__((amdgpu_waves_per_eu(pl
       if constexpr (NY) yb = yv[q];
       if constexpr (YR) ab = yb + (Yv - yb) * (1.0 / 3.0);
       if constexpr (YA) yb = ab;
-      if constexpr (PM == 3) {
+      if constexpr (PM == 3 || (PM == 2 && MIX)) {
         if (a.accdst)
           st_stream<NT_PLANE_STA>(byte_off(a.accdst + (base + q * C::NTHR), bs), ab + a.cb * k);
       } else {
@@ -1049,20 +1067,28 @@ void launch_plane_t(const KDims& d, const KTab& t, const KCoef& c, const StageAr
 
 // the FP64 RK4 stages in the paired order (launch_plane has checked the shape,
 // the stage form of each mode and that the stage matches the mode)
-template <int NT, bool AN>
+template <int NT, bool AN, typename TY, typename TO, typename TC>
 void launch_plane_paired(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
-  if constexpr (2 * NT >= 16) {
+  if constexpr (sizeof(TY) == 8 && sizeof(TO) == 4) {
+    // the mixed path's first stage (FP64 state in, checked by launch_plane)
+    if constexpr (2 * NT >= 16) launch_plane_t<NT, false, 0, TY, TO, TC, AN, 1>(d, t, c, a, s);
+  } else if constexpr (2 * NT >= 16) {
     switch (a.pair_mode) {
-      case 1: launch_plane_t<NT, false, 0, double, double, double, AN, 1>(d, t, c, a, s); break;
+      case 1: launch_plane_t<NT, false, 0, TY, TO, TC, AN, 1>(d, t, c, a, s); break;
       case 2:
-        if (a.accrec)
-          launch_plane_t<NT, false, 2, double, double, double, AN, 2>(d, t, c, a, s);
-        else if (a.accsrc)
-          launch_plane_t<NT, true, 1, double, double, double, AN, 2>(d, t, c, a, s);
-        else
-          launch_plane_t<NT, false, 0, double, double, double, AN, 2>(d, t, c, a, s);
+        if constexpr (sizeof(TO) == 8) {
+          if (a.accrec) {
+            launch_plane_t<NT, false, 2, TY, TO, TC, AN, 2>(d, t, c, a, s);
+            break;
+          }
+          if (!a.accsrc) {
+            launch_plane_t<NT, false, 0, TY, TO, TC, AN, 2>(d, t, c, a, s);
+            break;
+          }
+        }
+        launch_plane_t<NT, true, 1, TY, TO, TC, AN, 2>(d, t, c, a, s);
         break;
-      default: launch_plane_t<NT, true, 0, double, double, double, AN, 3>(d, t, c, a, s); break;
+      default: launch_plane_t<NT, true, 0, TY, TO, TC, AN, 3>(d, t, c, a, s); break;
     }
   }
 }
@@ -1071,12 +1097,12 @@ template <int NT, typename TY, typename TO, typename TC>
 void launch_plane_nt(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a, hipStream_t s) {
   const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
   const bool an = d.scattering && c.aniso && a.mode != PM_APPLY;
+  if (a.pair_mode) {
+    if (an) launch_plane_paired<NT, true, TY, TO, TC>(d, t, c, a, s);
+    else launch_plane_paired<NT, false, TY, TO, TC>(d, t, c, a, s);
+    return;
+  }
   if constexpr (sizeof(TY) == 8 && sizeof(TO) == 8) {
-    if (a.pair_mode) {
-      if (an) launch_plane_paired<NT, true>(d, t, c, a, s);
-      else launch_plane_paired<NT, false>(d, t, c, a, s);
-      return;
-    }
     if (na && ny && a.accsrc == a.ysrc) {  // y is the accumulator source: load it once (AB2 step 3 % faster)
       if (an) launch_plane_t<NT, true, 4, TY, TO, TC, true>(d, t, c, a, s);
       else launch_plane_t<NT, true, 4, TY, TO, TC, false>(d, t, c, a, s);
@@ -1117,19 +1143,23 @@ hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const Sta
     // the FP64 RK4 stage forms: 1 (no accumulator, no y), 2 (stage 1 on a
     // paired state: no accumulator, no y; stage 2: accumulator recovered from y;
     // stage 3: accumulator and y), 3 (accumulator, no y, no ynext)
+    // (mixed path: stage 1 also writes the accumulator; no recovered
+    // accumulator, the state F always in the plain order)
     const bool na = a.accsrc != nullptr, ny = a.ysrc != nullptr;
-    const bool s1 = !na && !ny && !a.accdst && a.ynext;
+    const bool s1 = !na && !ny && (a.mixed || !a.accdst) && a.ynext;
     bool form = false;
     switch (a.pair_mode) {
       case 1: form = s1; break;
       case 2:
-        form = (s1 && a.pair_all) ||
-               (ny && a.accdst && a.ynext && (a.accrec ? !na : (na && a.accsrc != a.ysrc)));
+        form = (s1 && a.pair_all && !a.mixed) ||
+               (ny && a.accdst && a.ynext && (a.accrec ? !na && !a.mixed : (na && a.accsrc != a.ysrc)));
         break;
       case 3: form = na && !ny && a.accdst && !a.ynext; break;
       default: break;
     }
-    if (!form || a.mixed || a.mode != PM_STAGE || !paired_order_ok(d) || d.n_Ph != 2 * d.n_Th)
+    // (mixed path: the first stage reads the FP64 state, the others the FP32 copy)
+    const bool mixed_ok = !a.mixed || (!a.pair_all && (a.pair_mode == 1) == !a.yin_f32);
+    if (!form || !mixed_ok || a.mode != PM_STAGE || !paired_order_ok(d) || d.n_Ph != 2 * d.n_Th)
       return hipErrorInvalidValue;
   }
   switch (d.n_Th) {

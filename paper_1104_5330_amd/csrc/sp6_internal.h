@@ -144,7 +144,7 @@ bool sphere_fusable(const KDims& d, bool mixed);
 hipError_t launch_sphere(const KDims& d, const KTab& t, const double* Y, double* T, double coef_sign,
                          bool mask_in, double in_scale, hipStream_t s, bool paired = false);
 hipError_t launch_sphere_mixed(const KDims& d, const KTab& t, const void* Y, bool y_f32, float* T,
-                               hipStream_t s);
+                               hipStream_t s, bool paired = false);
 hipError_t launch_radial(const KDims& d, const KTab& t, const double* Y, double* T, bool accum,
                          bool transpose, bool mask_in, double in_scale, hipStream_t s);
 hipError_t launch_plane(const KDims& d, const KTab& t, const KCoef& c, const StageArgs& a,

@@ -153,23 +153,28 @@ def test_paired_order_host_build(tmp_path, root):
 #include <cstdio>
 int main() {
   int bad = 0;
-  for (int nPh = 16; nPh <= 64; nPh *= 2) {
-    const int hP = nPh / 2;
-    int seen[64] = {0};
-    for (int phi = 0; phi < nPh; ++phi) {
-      const int p = paired_pos(phi, hP);
-      bad += p < 0 || p >= nPh;
-      if (p >= 0 && p < nPh) seen[p]++;
-      bad += paired_phi(p, hP) != phi;
-    }
-    for (int p = 0; p < nPh; ++p) bad += seen[p] != 1;
-    for (int g = 0; g < hP / 4; ++g)
-      for (int col = 0; col < 8; ++col) {
-        const int phi = 4 * g + (col & 3) + ((col & 4) ? hP : 0);
-        bad += paired_pos(phi, hP) != 8 * g + col;
+  for (int G = 4; G <= 8; G *= 2)
+    for (int nPh = 16; nPh <= 64; nPh *= 2) {
+      const int hP = nPh / 2;
+      int seen[64] = {0};
+      for (int phi = 0; phi < nPh; ++phi) {
+        const int p = paired_pos(phi, hP, G);
+        bad += p < 0 || p >= nPh;
+        if (p >= 0 && p < nPh) seen[p]++;
+        bad += paired_phi(p, hP, G) != phi;
+        bad += p / nPh != 0;
       }
-  }
+      for (int p = 0; p < nPh; ++p) bad += seen[p] != 1;
+      // tile t of a row: columns G t .. G t + G - 1 and their partners at + hP,
+      // stored side by side from position 2 G t
+      for (int t = 0; t < hP / G; ++t)
+        for (int col = 0; col < 2 * G; ++col) {
+          const int phi = G * t + (col % G) + (col >= G ? hP : 0);
+          bad += paired_pos(phi, hP, G) != 2 * G * t + col;
+        }
+    }
   static_assert(paired_pos(37, 32) == 12 + 1, "Phi = 37 of 64: group 1 of the second half");
+  static_assert(paired_pos(37, 32, 8) == 8 + 5, "FP32 groups of eight: Phi = 37 is 5 into the first group's partner");
   std::printf("%d\n", bad);
   return bad;
 }
