@@ -29,7 +29,8 @@ def l2rel(a, b):
 
 
 def to_dev(x):
-    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+    # a writable C-order copy (read-only views, e.g. broadcasts, are copied too)
+    return torch.from_numpy(np.array(x, dtype=np.float64, order="C")).cuda()
 
 
 def to_host(t):
