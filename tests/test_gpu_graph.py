@@ -13,7 +13,7 @@ import torch
 
 import synth
 from oracle import step
-from tests.gpu_util import need_gpu, maxrel, to_dev, to_host, oracle_grid, small, banner
+from tests.gpu_util import need_gpu, maxrel, to_dev, to_host, oracle_grid, small, banner, stable_dt
 
 pytestmark = pytest.mark.gpu
 
@@ -98,4 +98,33 @@ def test_graph_replays_equal_eager(form, precision):
         err = maxrel(to_host(Fg), want)
         banner(f"graph rk4 fp64: 7 steps vs oracle {err:.2e}")
         assert err <= TOL
+    del graph
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_equal_eager_sphere64(precision):
+    """The 32 x 64 position sphere, no filter: the captured two-step call holds the
+    state in the paired in-plane order between its steps (FP64) and the stage
+    buffers in it (both paths); every replay equals the eager call bit for bit."""
+    from paper_1104_5330_amd import Sp6Grid
+    cfg = small(5, n_eps=1, n_r=3, n_Theta=8, n_Phi=16)
+    G = Sp6Grid.from_config(cfg, precision=precision, scattering=True)
+    F = synth.fields.random_state(cfg, 13)
+    k, s, e = synth.fields.random_coeffs(cfg, 14)
+    G.set_coefficients(to_dev(k), to_dev(s), to_dev(e))
+    dt = stable_dt(cfg)
+    Fe, Fg = to_dev(F), to_dev(F)
+    G.step(Fe, dt, 1)
+    G.step(Fg, dt, 1)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        G.step(Fg, dt, 2)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        G.step(Fe, dt, 2)
+        torch.cuda.synchronize()
+        banner(f"graph sphere64 {precision}: replay {rep}")
+        assert torch.equal(Fe, Fg), f"replay {rep} differs from the eager steps"
     del graph
