@@ -439,12 +439,12 @@ __global__ __launch_bounds__(CB) void k_filter_theta(KDims d, KTab t, double* __
 // partner is col ^ R.  For R < n_Phi / 2 a tile is two runs of R columns of one
 // Theta row, m0 .. m0 + R - 1 and their partners; otherwise whole Theta rows.
 
-// tiles per 128-byte line of a column run (R = CW / 2 values of type TI)
-template <int CW, typename TI>
-constexpr int sphere_group() {
-  constexpr int g = 128 / ((CW / 2) * int(sizeof(TI)));
-  return g < 1 ? 1 : (g > 8 ? 8 : g);
-}
+// consecutive tiles of a fused theta-phi pass taken by one XCD (blocks b, b + 8,
+// ... of one XCD): 16, measured against the tiles that share one 128-byte line
+// of a column run (2 FP64, 4 FP32 on the 16 x 32 sphere; FP64 236.6 -> 223.8
+// us, FP32 163.4 -> 148.0 us per launch on the 8-group workloads) and on the
+// 32 x 64 sphere (below)
+constexpr int XCD_TILE_GROUP = 16;
 
 template <int NTH, int CW, typename TC>
 struct SPC {
@@ -466,9 +466,9 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
   using C = SPC<NTH, CW, TC>;
   constexpr int L = C::L, NPH = C::NPH;
   __shared__ __align__(16) TC sY[C::NE];
-  // blocks b, b + 8, ..., b + 8 (G - 1) run on the same XCD; they take the G
-  // consecutive tiles whose column runs (R = CW / 2 values) share 128-byte lines
-  constexpr int G = sphere_group<CW, TI>();
+  // blocks b, b + 8, ..., b + 8 (G - 1) run on the same XCD and take G
+  // consecutive tiles (those whose column runs share 128-byte lines among them)
+  constexpr int G = XCD_TILE_GROUP;
   // (descending: block b takes the place of block gridDim - 1 - b; the grid is a
   // multiple of 8 G, so the XCD pairing is kept)
   const int b = d.rev ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
@@ -597,9 +597,6 @@ __global__ __launch_bounds__((SPC<NTH, CW, TC>::NTHR)) void k_sphere(KDims d, KT
 // written once (16 bytes per point in FP64 instead of 40 for the two separate
 // passes).
 
-// consecutive tiles of the fused 32 x 64 pass taken by one XCD (k_sphere64)
-constexpr int S64_XCD_GROUP = 16;
-
 template <int CW, int NW_, typename TC>
 struct S64 {
   static constexpr int NTH = 32, NPH = 64, L = 64;
@@ -653,7 +650,7 @@ __global__ __launch_bounds__(64 * NW) void k_sphere64(KDims d, KTab t, const TI*
   // measured 6.10 -> 5.57 ms (FP64) and 3.38 -> 3.16 ms (FP32) per launch on
   // the paired order against G = 4, the tiles that share one 128-byte line of the
   // plain order (where wider groups made no difference)
-  constexpr int G = S64_XCD_GROUP;
+  constexpr int G = XCD_TILE_GROUP;
   const int b = d.rev ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
   const int tile = (b / (8 * G)) * (8 * G) + (b % 8) * G + (b / 8) % G;
   if (tile >= ntiles) return;
@@ -902,7 +899,7 @@ hipError_t launch_sphere64_t(const KDims& d, const KTab& t, const TI* Y, TC* T, 
   // FP32 tiles is the caller's state, in the plain order
   if (paired && (CW / 2 != (sizeof(TI) == 8 ? 4 : 8) || sizeof(TC) != sizeof(TI))) return hipErrorInvalidValue;
   const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
-  constexpr int64_t GB = 8 * S64_XCD_GROUP;
+  constexpr int64_t GB = 8 * XCD_TILE_GROUP;
   const int64_t nb = (ntiles + GB - 1) / GB * GB;
   if (nb > INT32_MAX) return hipErrorInvalidValue;
   k_sphere64<CW, NW, TI, TC><<<unsigned(nb), 64 * NW, 0, s>>>(d, t, Y, T, coef_sign, mask_in, in_scale, int(ntiles),
@@ -928,7 +925,7 @@ template <int NTH, int CW, typename TI, typename TC>
 hipError_t launch_sphere_t(const KDims& d, const KTab& t, const void* Y, void* T, double coef_sign, bool mask_in,
                            double in_scale, hipStream_t s) {
   const int64_t ntiles = int64_t(d.n_eps) * d.n_r * (d.plane / CW);
-  constexpr int64_t GB = 8 * sphere_group<CW, TI>();
+  constexpr int64_t GB = 8 * XCD_TILE_GROUP;
   const int64_t nb = (ntiles + GB - 1) / GB * GB;
   if (nb > INT32_MAX) return hipErrorInvalidValue;
   k_sphere<NTH, CW, TI, TC><<<unsigned(nb), SPC<NTH, CW, TC>::NTHR, 0, s>>>(
