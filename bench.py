@@ -124,7 +124,7 @@ def run_steps(cfg, precision, scattering, steps, warmup, F0=None, kernel=None, e
     if F0 is None:
         F0 = synth.fields.shell_state(cfg, device=dev)
     if coeffs is None:
-        coeffs = [torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)]
+        coeffs = [torch.tensor(a, device=dev) for a in synth.fields.coefficients(cfg)]
     G = Sp6Grid.from_config(cfg, precision=precision, bc=True, scattering=scattering)
     G.set_coefficients(*coeffs)
     if kernel is not None:
@@ -276,8 +276,9 @@ def form_shell(args):
         cfg = synth.config(n)
         steps = math.ceil(cfg.t_end / cfg.dt)
         G = Sp6Grid.from_config(cfg, scattering=True, filter=2)
-        G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
-        g_in, g_out = (torch.as_tensor(a, device=dev) for a in synth.fields.lambert_inflow(cfg))
+        # (copies: some of these fields are read-only numpy views)
+        G.set_coefficients(*(torch.tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
+        g_in, g_out = (torch.tensor(a, device=dev) for a in synth.fields.lambert_inflow(cfg))
         G.set_inflow(g_in, g_out)
         F = torch.zeros(cfg.shape, dtype=torch.float64, device=dev)
         G.project_inflow(F)
@@ -314,7 +315,7 @@ def form_ab2(args):
     cfg = synth.config(2)
     dev = torch.device("cuda", 0)
     G = Sp6Grid.from_config(cfg, scattering=False)
-    G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
+    G.set_coefficients(*(torch.tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
     F = synth.fields.shell_state(cfg, device=dev)
     H = torch.empty_like(F)
     G.step_ab2(F, H, cfg.dt, max(args.warmup, 1), start=True)
@@ -344,7 +345,7 @@ def form_implicit(args):
     cfg = synth.config(2)
     dev = torch.device("cuda", 0)
     G = Sp6Grid.from_config(cfg, scattering=False)
-    G.set_coefficients(*(torch.as_tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
+    G.set_coefficients(*(torch.tensor(a, device=dev) for a in synth.fields.coefficients(cfg)))
     F = synth.fields.shell_state(cfg, device=dev)
     G.step_radial_implicit(F, cfg.dt, max(args.warmup, 1))
     torch.cuda.synchronize()
